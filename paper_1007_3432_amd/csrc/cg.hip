@@ -1,0 +1,332 @@
+// Conjugate gradient on Q = M^T M (Sec. 4.1): FP64 Hestenes-Stiefel CG and
+// mixed-precision CG with FP64 reliable updates, all state device-resident.
+//
+// One iteration is two kernels:
+//   A  p_new = r + beta p_old, q = Q p_new, x += alpha_prev p_old, p.q
+//      (the fused sweep with OpPhaseA); its last block sets alpha = rho/p.q
+//   B  r -= alpha q, r.r; its last block sets beta, rho and the done flag
+// Every kernel reads the scalars it needs from device memory and returns at
+// once when the solve has finished, so the host enqueues whole chunks of
+// iterations and looks at the state only between chunks (one chunk ahead).
+// A chunk ends with a fold (x += pending alpha p [+ x_lo]) and an FP64
+// true-residual sweep: always in the mixed solver (the reliable update),
+// only after an iterated convergence in the FP64 solver.
+#include <cmath>
+
+#include "sweep.h"
+
+namespace hub {
+
+Link16 make_link16(const Geom& g, const void* links);
+
+__global__ void k_zero_scalars(CGScalars* sc) {
+    uint32_t* w = reinterpret_cast<uint32_t*>(sc);
+    for (int k = threadIdx.x; k < (int)(sizeof(CGScalars) / 4); k += blockDim.x) w[k] = 0;
+}
+
+// r = phi, p = 0, x = 0 (x_lo = 0), |phi|^2.
+template <class RVec>
+__global__ __launch_bounds__(256) void k_init(CGScalars* sc, const double* __restrict__ phi,
+                                              RVec* __restrict__ r, RVec* __restrict__ p0,
+                                              double* __restrict__ x, float* __restrict__ xlo,
+                                              int V, double tol2, int max_iter,
+                                              double* partials) {
+    double part = 0.0;
+    for (int i = blockIdx.x * 256 + threadIdx.x; i < V; i += gridDim.x * 256) {
+        const double f = phi[i];
+        r[i] = (RVec)f;
+        p0[i] = (RVec)0;
+        x[i] = 0.0;
+        if (xlo) xlo[i] = 0.0f;
+        part += f * f;
+    }
+    double total;
+    if (grid_sum_last<256>(part, partials, &sc->ticket, total) && threadIdx.x == 0) {
+        sc->phi2 = total;
+        sc->rho = total;
+        sc->rho_prev = total;
+        sc->rho_true = total;
+        sc->alpha = 0.0;
+        sc->beta = 0.0;
+        sc->tol2phi2 = tol2 * total;
+        sc->iter = 0;
+        sc->max_iter = max_iter;
+        sc->reliable_updates = 0;
+        sc->done = !std::isfinite(total) ? kDoneBreakdown
+                                         : (total == 0.0 ? kDoneConverged : kRunning);
+    }
+}
+
+// r -= alpha q, rho' = r.r (FP64 accumulation).
+template <class Vec>
+__global__ __launch_bounds__(256) void k_phaseB(CGScalars* sc, Vec* __restrict__ r,
+                                                const Vec* __restrict__ q, int V,
+                                                double* partials) {
+    if (sc->done != kRunning) return;
+    const Vec alpha = (Vec)sc->alpha;
+    double part = 0.0;
+    for (int i = blockIdx.x * 256 + threadIdx.x; i < V; i += gridDim.x * 256) {
+        const Vec rv = r[i] - alpha * q[i];
+        r[i] = rv;
+        part += (double)rv * (double)rv;
+    }
+    double total;
+    if (grid_sum_last<256>(part, partials, &sc->ticket, total) && threadIdx.x == 0) {
+        if (!std::isfinite(total)) {
+            sc->done = kDoneBreakdown;
+            return;
+        }
+        sc->rho_prev = sc->rho;
+        sc->rho = total;
+        sc->beta = total / sc->rho_prev;
+        sc->iter += 1;
+        if (total <= sc->tol2phi2)
+            sc->done = kDoneIterConverged;
+        else if (sc->iter >= sc->max_iter)
+            sc->done = kDoneMaxIter;
+    }
+}
+
+// x += alpha p (+ x_lo, then x_lo = 0): the pending update, in FP64.
+template <class PVec>
+__global__ __launch_bounds__(256) void k_fold(CGScalars* sc, int mode, double* __restrict__ x,
+                                              float* __restrict__ xlo,
+                                              const PVec* __restrict__ p0,
+                                              const PVec* __restrict__ p1, int V) {
+    if (!mode_runs(mode, sc->done)) return;
+    const double alpha = sc->alpha;
+    const PVec* p = (sc->iter & 1) ? p1 : p0;
+    for (int i = blockIdx.x * 256 + threadIdx.x; i < V; i += gridDim.x * 256) {
+        double v = x[i] + alpha * (double)p[i];
+        if (xlo) {
+            v += (double)xlo[i];
+            xlo[i] = 0.0f;
+        }
+        x[i] = v;
+    }
+}
+
+namespace {
+
+// Pinned per-thread snapshot buffers and events for the chunk pipeline.
+struct HostCtx {
+    int device = -1;
+    CGScalars* snap = nullptr;  // [2], pinned
+    hipEvent_t ev[2] = {nullptr, nullptr};
+    hipEvent_t t0 = nullptr, t1 = nullptr;
+    ~HostCtx() {
+        if (device < 0) return;
+        (void)hipSetDevice(device);
+        if (snap) (void)hipHostFree(snap);
+        for (auto e : {ev[0], ev[1], t0, t1})
+            if (e) (void)hipEventDestroy(e);
+    }
+    hub_status ensure() {
+        int dev = 0;
+        HUB_HIP(hipGetDevice(&dev));
+        if (dev == device) return HUB_OK;
+        if (device >= 0) return set_error(HUB_E_INVALID, "hub_cg_solve: one device per thread");
+        HUB_HIP(hipHostMalloc((void**)&snap, 2 * sizeof(CGScalars), hipHostMallocDefault));
+        HUB_HIP(hipEventCreateWithFlags(&ev[0], hipEventDisableTiming));
+        HUB_HIP(hipEventCreateWithFlags(&ev[1], hipEventDisableTiming));
+        HUB_HIP(hipEventCreate(&t0));
+        HUB_HIP(hipEventCreate(&t1));
+        device = dev;
+        return HUB_OK;
+    }
+};
+
+thread_local HostCtx g_ctx;
+
+#define HUB_TRY(expr)                       \
+    do {                                    \
+        hub_status s_ = (expr);             \
+        if (s_ != HUB_OK) return s_;        \
+    } while (0)
+
+template <class Vec, class Lnk>
+struct Solver {
+    const Geom& g;
+    const hub_cg_opts& o;
+    hipStream_t st;
+    SweepPlan P;
+    int egrid;
+    // device buffers
+    CGScalars* sc;
+    double* partials;
+    const double* phi;
+    double* x;
+    const double* A64;
+    Lnk lk;
+    Vec *r, *p0, *p1, *q;
+    float* xlo;        // mixed only
+    double* yscratch;  // generic sweeps only (holds V doubles)
+
+    hub_status fold_and_residual(int mode) {
+        k_fold<Vec><<<egrid, 256, 0, st>>>(sc, mode, x, xlo, p0, p1, g.V);
+        OpResidual<Vec> op{sc, x, phi, r, Link64{A64}, mode};
+        return launch_q(g, P, op, yscratch, partials, &sc->ticket, st);
+    }
+
+    hub_status chunk(int iters, CGScalars* snap, hipEvent_t ev, bool mixed) {
+        OpPhaseA<Vec, Vec, typename std::conditional<sizeof(Vec) == 8, double, float>::type, Lnk>
+            opA{};
+        opA.sc = sc;
+        opA.r = r;
+        opA.pbuf0 = p0;
+        opA.pbuf1 = p1;
+        opA.q = q;
+        if constexpr (sizeof(Vec) == 8) opA.x = x; else opA.x = xlo;
+        opA.lk = lk;
+        for (int k = 0; k < iters; ++k) {
+            HUB_TRY(launch_q(g, P, opA, (Vec*)yscratch, partials, &sc->ticket, st));
+            k_phaseB<Vec><<<egrid, 256, 0, st>>>(sc, r, q, g.V, partials);
+        }
+        HUB_TRY(fold_and_residual(mixed ? kModeReliable : kModeCheck));
+        HUB_HIP(hipMemcpyAsync(snap, sc, sizeof(CGScalars), hipMemcpyDeviceToHost, st));
+        HUB_HIP(hipEventRecord(ev, st));
+        return HUB_OK;
+    }
+};
+
+template <class Vec, class Lnk>
+hub_status run_solver(Solver<Vec, Lnk>& S, bool mixed, hub_cg_stats* out) {
+    const Geom& g = S.g;
+    const hub_cg_opts& o = S.o;
+    hipStream_t st = S.st;
+    HostCtx& H = g_ctx;
+    HUB_HIP(hipEventRecord(H.t0, st));
+    k_zero_scalars<<<1, 64, 0, st>>>(S.sc);
+    k_init<Vec><<<S.egrid, 256, 0, st>>>(S.sc, S.phi, S.r, S.p0, S.x, S.xlo, g.V,
+                                         o.tol * o.tol, o.max_iter, S.partials);
+    HUB_HIP(hipGetLastError());
+    const int C = mixed ? o.reliable_every : 50;
+    // Every chunk either runs at least one iteration or ends the solve, so
+    // this bound is never reached by a healthy solve.
+    const long long max_chunks = 2LL * (o.max_iter / C + 2) + 8;
+    HUB_TRY(S.chunk(C, &H.snap[0], H.ev[0], mixed));
+    HUB_TRY(S.chunk(C, &H.snap[1], H.ev[1], mixed));
+    long long enq = 2;
+    int cur = 0;
+    CGScalars s{};
+    for (;;) {
+        HUB_HIP(hipEventSynchronize(H.ev[cur]));
+        s = H.snap[cur];
+        if (s.done >= kDoneConverged) break;
+        if (enq >= max_chunks) {
+            (void)hipStreamSynchronize(st);
+            return set_error(HUB_E_NOCONV, "hub_cg_solve: chunk limit reached");
+        }
+        HUB_TRY(S.chunk(C, &H.snap[cur], H.ev[cur], mixed));
+        ++enq;
+        cur ^= 1;
+    }
+    if (s.done != kDoneConverged) HUB_TRY(S.fold_and_residual(kModeFinal));
+    HUB_HIP(hipMemcpyAsync(&H.snap[cur], S.sc, sizeof(CGScalars), hipMemcpyDeviceToHost, st));
+    HUB_HIP(hipEventRecord(H.t1, st));
+    HUB_HIP(hipStreamSynchronize(st));
+    s = H.snap[cur];
+    float ms = 0.0f;
+    HUB_HIP(hipEventElapsedTime(&ms, H.t0, H.t1));
+    hub_cg_stats stats{};
+    stats.iters = s.iter;
+    stats.reliable_updates = s.reliable_updates;
+    stats.true_rel_resid = s.phi2 > 0 ? std::sqrt(s.rho_true / s.phi2) : 0.0;
+    stats.ms = ms;
+    stats.status = s.done == kDoneConverged ? HUB_OK : HUB_E_NOCONV;
+    if (out) *out = stats;
+    if (stats.status != HUB_OK)
+        return set_error(HUB_E_NOCONV,
+                         "CG did not converge: %d iterations, true relative residual %.3e%s",
+                         s.iter, stats.true_rel_resid,
+                         s.done == kDoneBreakdown ? " (breakdown)" : "");
+    return HUB_OK;
+}
+
+}  // namespace
+
+hub_status cg_solve(const Geom& g, const double* sigma, const double* phi, double* x,
+                    const hub_cg_opts& o, hub_cg_stats* out, hipStream_t st) {
+    HUB_TRY(g_ctx.ensure());
+    const bool mixed = o.bulk == HUB_F32;
+    const size_t V = (size_t)g.V;
+    const size_t vb = mixed ? 4 : 8;
+    const SweepPlan P = plan_sweep(g);
+    auto al = [](size_t b) { return (b + 255) & ~size_t(255); };
+    size_t off = 0;
+    const size_t o_sc = off; off += al(sizeof(CGScalars));
+    const size_t o_part = off; off += al(sizeof(double) * max_partials(g));
+    const size_t o_A64 = off; off += al(8 * V);
+    const size_t o_lnk = off; off += mixed ? al(dtype_size(o.link) * V) : 0;
+    const size_t o_r = off; off += al(vb * V);
+    const size_t o_p0 = off; off += al(vb * V);
+    const size_t o_p1 = off; off += al(vb * V);
+    const size_t o_q = off; off += al(vb * V);
+    const size_t o_xlo = off; off += mixed ? al(4 * V) : 0;
+    const size_t o_y = off; off += P.fused ? 0 : al(8 * V);
+    char* ws = nullptr;
+    if (hipMallocAsync((void**)&ws, off, st) != hipSuccess) {
+        (void)hipGetLastError();
+        return set_error(HUB_E_NOMEM, "hub_cg_solve: cannot allocate %zu bytes of workspace", off);
+    }
+    hub_status result = HUB_OK;
+    const double* A64 = (const double*)(ws + o_A64);
+    result = launch_links(g, sigma, ws + o_A64, HUB_F64, st);
+    if (result == HUB_OK && mixed) result = launch_links(g, sigma, ws + o_lnk, o.link, st);
+    if (result == HUB_OK) {
+        if (!mixed) {
+            Solver<double, Link64> S{g, o, st, P, elementwise_grid(g)};
+            S.sc = (CGScalars*)(ws + o_sc);
+            S.partials = (double*)(ws + o_part);
+            S.phi = phi;
+            S.x = x;
+            S.A64 = A64;
+            S.lk = Link64{A64};
+            S.r = (double*)(ws + o_r);
+            S.p0 = (double*)(ws + o_p0);
+            S.p1 = (double*)(ws + o_p1);
+            S.q = (double*)(ws + o_q);
+            S.xlo = nullptr;
+            S.yscratch = P.fused ? nullptr : (double*)(ws + o_y);
+            result = run_solver(S, false, out);
+        } else if (o.link == HUB_F32) {
+            Solver<float, Link32> S{g, o, st, P, elementwise_grid(g)};
+            S.sc = (CGScalars*)(ws + o_sc);
+            S.partials = (double*)(ws + o_part);
+            S.phi = phi;
+            S.x = x;
+            S.A64 = A64;
+            S.lk = Link32{(const float*)(ws + o_lnk)};
+            S.r = (float*)(ws + o_r);
+            S.p0 = (float*)(ws + o_p0);
+            S.p1 = (float*)(ws + o_p1);
+            S.q = (float*)(ws + o_q);
+            S.xlo = (float*)(ws + o_xlo);
+            S.yscratch = P.fused ? nullptr : (double*)(ws + o_y);
+            result = run_solver(S, true, out);
+        } else {
+            Solver<float, Link16> S{g, o, st, P, elementwise_grid(g)};
+            S.sc = (CGScalars*)(ws + o_sc);
+            S.partials = (double*)(ws + o_part);
+            S.phi = phi;
+            S.x = x;
+            S.A64 = A64;
+            S.lk = make_link16(g, ws + o_lnk);
+            S.r = (float*)(ws + o_r);
+            S.p0 = (float*)(ws + o_p0);
+            S.p1 = (float*)(ws + o_p1);
+            S.q = (float*)(ws + o_q);
+            S.xlo = (float*)(ws + o_xlo);
+            S.yscratch = P.fused ? nullptr : (double*)(ws + o_y);
+            result = run_solver(S, true, out);
+        }
+    }
+    hipError_t e = hipFreeAsync(ws, st);
+    hipError_t e2 = hipStreamSynchronize(st);
+    if (result == HUB_OK && (e != hipSuccess || e2 != hipSuccess))
+        return set_error(HUB_E_DEVICE, "hub_cg_solve: %s",
+                         hipGetErrorString(e != hipSuccess ? e : e2));
+    return result;
+}
+
+}  // namespace hub

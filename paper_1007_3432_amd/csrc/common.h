@@ -1,0 +1,134 @@
+// Shared device/host definitions of libhub (gfx950).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <hip/hip_fp16.h>
+#include <stdint.h>
+
+#include "hub.h"
+
+namespace hub {
+
+// Lattice geometry and operator constants, passed to kernels by value.
+struct Geom {
+    int d;          // spatial dimensions
+    int nx;         // spatial extent
+    int nt;         // time slices
+    int vs;         // nx^d
+    int V;          // vs * nt
+    double kappa;   // dtau * t_hop
+    double lscale;  // exp(dtau * mu)
+    double b;       // Hubbard-Stratonovich coupling sqrt(2 (exp(-dtau U) - 1))
+};
+
+// Device-resident solver state of one CG solve.  Every field is written by
+// exactly one thread: thread 0 of the block that finishes a grid reduction
+// last, or an initialisation kernel.
+struct CGScalars {
+    double rho;        // current iterated r.r (FP64 accumulation)
+    double rho_prev;   // r.r of the previous iteration
+    double alpha;      // step length still to be added to x (0 once folded)
+    double beta;       // coefficient of the next p = r + beta p
+    double phi2;       // |phi|^2
+    double tol2phi2;   // tol^2 |phi|^2
+    double rho_true;   // |phi - Q x|^2 of the last true-residual recompute
+    double pq;         // last p.Qp
+    int32_t iter;      // iterations completed
+    int32_t max_iter;
+    int32_t done;      // see kDone* below
+    int32_t reliable_updates;
+    uint32_t ticket;   // grid-reduction arrival counter (reset by the last)
+    int32_t pad[3];
+};
+
+enum : int32_t {
+    kRunning = 0,
+    kDoneIterConverged = 1,  // iterated residual met tol: verify
+    kDoneConverged = 2,      // true residual met tol
+    kDoneBreakdown = 3,      // p.Qp <= 0 or a non-finite scalar
+    kDoneMaxIter = 4,
+};
+
+// When the fold / true-residual kernels run.
+enum : int32_t {
+    kModeReliable = 0,  // periodic reliable update: run while done <= 1
+    kModeCheck = 1,     // verify an iterated convergence: run iff done == 1
+    kModeFinal = 2,     // end of solve: always run
+};
+
+__host__ __device__ inline int ceil_div(int a, int b) { return (a + b - 1) / b; }
+
+#if defined(__HIP_DEVICE_COMPILE__) || defined(__HIPCC__)
+// Workgroups are dispatched round-robin over the 8 XCDs of an MI355X, each
+// with its own L2.  Map hardware block ids so that every XCD receives a
+// contiguous range of logical tiles: neighbouring tiles (which share halo
+// sites) then hit in the same L2.
+__device__ inline int xcd_remap(int bid, int nblocks) {
+    constexpr int kXcd = 8;
+    const int q = nblocks / kXcd, r = nblocks % kXcd;
+    const int x = bid % kXcd, k = bid / kXcd;
+    return x * q + (x < r ? x : r) + k;
+}
+
+// Wrap an index that is at most one period out of [0, n).
+__device__ inline int wrap1(int v, int n) {
+    return v < 0 ? v + n : (v >= n ? v - n : v);
+}
+
+// Sum over a 64-wide wavefront, result valid in every lane.
+__device__ inline double wave_sum(double v) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    return v;
+}
+
+// Deterministic block sum (fixed tree); result valid in thread 0.
+template <int BLOCK>
+__device__ inline double block_sum(double v) {
+    static_assert(BLOCK % 64 == 0 && BLOCK <= 1024, "block must be whole waves");
+    __shared__ double red[BLOCK / 64];
+    v = wave_sum(v);
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    __syncthreads();  // red[] may still be read by a previous call
+    if (lane == 0) red[wid] = v;
+    __syncthreads();
+    double s = 0.0;
+    if (threadIdx.x == 0) {
+#pragma unroll
+        for (int w = 0; w < BLOCK / 64; ++w) s += red[w];
+    }
+    return s;
+}
+
+// Single-pass grid reduction: every block deposits its sum, the block that
+// arrives last adds the deposits in block-id order (deterministic for a
+// given grid) and returns true with the total in `total` (valid in thread
+// 0).  The arrival counter is reset for the next launch.
+template <int BLOCK>
+__device__ inline bool grid_sum_last(double part, double* partials,
+                                     uint32_t* ticket, double& total) {
+    __shared__ int am_last;
+    const double bs = block_sum<BLOCK>(part);
+    if (threadIdx.x == 0) {
+        __hip_atomic_store(&partials[blockIdx.x], bs, __ATOMIC_RELAXED,
+                           __HIP_MEMORY_SCOPE_AGENT);
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+        const uint32_t prev = __hip_atomic_fetch_add(
+            ticket, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+        am_last = (prev == gridDim.x - 1);
+    }
+    __syncthreads();
+    if (!am_last) return false;
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    double s = 0.0;
+    for (int k = threadIdx.x; k < (int)gridDim.x; k += BLOCK)
+        s += __hip_atomic_load(&partials[k], __ATOMIC_RELAXED,
+                               __HIP_MEMORY_SCOPE_AGENT);
+    total = block_sum<BLOCK>(s);
+    if (threadIdx.x == 0)
+        __hip_atomic_store(ticket, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    return true;
+}
+#endif
+
+}  // namespace hub

@@ -1,0 +1,53 @@
+// Host-side internals of libhub shared between translation units.
+#pragma once
+
+#include <string>
+
+#include "common.h"
+
+namespace hub {
+
+// Error reporting: thread-local message behind hub_last_error().
+hub_status set_error(hub_status st, const char* fmt, ...)
+    __attribute__((format(printf, 2, 3)));
+void clear_error();
+
+#define HUB_HIP(call)                                                        \
+    do {                                                                     \
+        hipError_t e_ = (call);                                              \
+        if (e_ != hipSuccess)                                                \
+            return ::hub::set_error(HUB_E_DEVICE, "%s failed: %s (%s:%d)",   \
+                                    #call, hipGetErrorString(e_), __FILE__,  \
+                                    __LINE__);                               \
+    } while (0)
+
+// Validates a lattice descriptor and fills the kernel geometry.
+hub_status make_geom(const hub_lattice* lat, Geom* g);
+
+// Bytes of one element of dtype.
+size_t dtype_size(hub_dtype t);
+
+// Accepted (vector, link) precision pairs of the apply calls.
+bool valid_pair(hub_dtype vec, hub_dtype link);
+
+// Kernel launchers (asynchronous on st; arguments already validated).
+hub_status launch_links(const Geom& g, const double* sigma, void* links,
+                        hub_dtype link, hipStream_t st);
+hub_status launch_apply_M(const Geom& g, const void* links, hub_dtype link,
+                          hub_dtype vec, const void* x, void* y, int transpose,
+                          hipStream_t st);
+// scratch: NULL, or at least mtm_scratch_bytes(g, vec) bytes of device memory.
+hub_status launch_apply_MtM(const Geom& g, const void* links, hub_dtype link,
+                            hub_dtype vec, const void* x, void* z, void* scratch,
+                            hipStream_t st);
+size_t mtm_scratch_bytes(const Geom& g, hub_dtype vec);
+
+// True when Q sweeps on this geometry use the fused single-pass kernel.
+bool mtm_fused(const Geom& g);
+
+// Blocking CG solve (arguments already validated).
+hub_status cg_solve(const Geom& g, const double* sigma, const double* phi,
+                    double* x, const hub_cg_opts& o, hub_cg_stats* out,
+                    hipStream_t st);
+
+}  // namespace hub

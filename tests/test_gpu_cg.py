@@ -1,0 +1,180 @@
+"""Parity of hub_cg_solve (FP64 and mixed precision) with the oracle.
+
+CG iterates depend on rounding order, so the GPU and oracle solutions are not
+bitwise equal.  What is unique is the solution of Q x = phi; each solve is
+checked by
+  * its true relative residual |phi - Q x| / |phi|, recomputed by the oracle
+    in FP64 (<= tol, with 10% slack for the rounding of the recompute itself,
+    at most ~cond(Q) * 1e-16),
+  * its distance to the oracle's own CG solution, which two solutions with
+    residual <= tol can differ by at most 2 cond(Q) tol,
+and, where the oracle finishes in seconds, by the iteration count.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_1007_3432_amd import hub, inputs
+from tests import hubtest
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-10
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _lib():
+    hubtest.ensure_built()
+    oracle.set_threads(16)
+
+
+def _problem(d, nx, nt, seed=0, **kw):
+    olat = oracle.Lattice(d, nx, nt, **kw)
+    lat = hub.lattice(d, nx, nt, olat.t_hop, olat.dtau, olat.U, olat.mu)
+    sigma, eta = inputs.sigma_eta(d, nx, nt, seed=seed)
+    A = oracle.links(olat, sigma)
+    phi = oracle.apply_Mt(olat, A, eta)
+    return olat, lat, sigma, A, phi
+
+
+def _solve(lat, sigma, phi, opts, raise_on_noconv=True):
+    x_d = hubtest.empty(lat.volume, hub.F64)
+    st = hub.hub_cg_solve(lat, hubtest.to_dev(sigma), hubtest.to_dev(phi), x_d, opts,
+                          raise_on_noconv=raise_on_noconv)
+    return x_d.cpu().numpy(), st
+
+
+def _true_resid(olat, A, phi, x):
+    return float(np.linalg.norm(phi - oracle.apply_MtM(olat, A, x)) / np.linalg.norm(phi))
+
+
+def _cond_estimate(olat, A, phi, x):
+    """cond(Q) >= lambda_max / lambda_min, estimated from power iterations on
+    Q and from the solution: lambda_min <= |phi| / |x|."""
+    v = inputs.random_vector(olat.volume, 99)
+    for _ in range(30):
+        v = oracle.apply_MtM(olat, A, v)
+        v /= np.linalg.norm(v)
+    lmax = float(np.dot(v, oracle.apply_MtM(olat, A, v)))
+    lmin_upper = np.linalg.norm(phi) / np.linalg.norm(x)
+    return lmax / lmin_upper
+
+
+CASES = [
+    ("c0_d1_32x64", (1, 32, 64)),
+    ("d1_256x128", (1, 256, 128)),
+    ("d3_8x80", (3, 8, 80)),
+    ("d3_4x7", (3, 4, 7)),
+    ("d2_6x10", (2, 6, 10)),
+    ("d1_37x9", (1, 37, 9)),
+]
+
+
+@pytest.mark.parametrize("name,shape", CASES, ids=[c[0] for c in CASES])
+@pytest.mark.parametrize("prec", ["f64", "f32", "f16"])
+def test_cg_parity(name, shape, prec):
+    olat, lat, sigma, A, phi = _problem(*shape)
+    hubtest.log_case(f"cg {name} {prec}")
+    x_o, res_o = oracle.cg(olat, A, phi, tol=TOL)
+    assert res_o.converged
+    if prec == "f64":
+        opts = hub.cg_opts(hub.F64)
+    else:
+        opts = hub.cg_opts(hub.F32, hub.F32 if prec == "f32" else hub.F16)
+    x, st = _solve(lat, sigma, phi, opts)
+    assert st["status"] == "HUB_OK"
+    assert st["true_rel_resid"] <= TOL
+    r = _true_resid(olat, A, phi, x)
+    assert r <= 1.1 * TOL, r
+    kappa = _cond_estimate(olat, A, phi, x_o)
+    assert hubtest.rel_err(x, x_o) <= 2 * kappa * TOL
+    if prec == "f64":
+        assert abs(st["iters"] - res_o.iters) <= 0.03 * res_o.iters + 3
+        assert st["reliable_updates"] >= 1
+    else:
+        # FP32 bulk converges within a modest factor of FP64's iterations
+        assert st["iters"] <= 3 * res_o.iters + 100
+        assert st["reliable_updates"] >= st["iters"] // 50
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_cg_full_size_c2(prec):
+    """d=3 16^3 x 160 (655 360 sites) at full size: the oracle checks the true
+    residual of the GPU solution."""
+    olat, lat, sigma, A, phi = _problem(3, 16, 160)
+    hubtest.log_case(f"cg c2 full {prec}")
+    opts = hub.cg_opts(hub.F64) if prec == "f64" else hub.cg_opts(hub.F32, hub.F32)
+    x, st = _solve(lat, sigma, phi, opts)
+    assert st["status"] == "HUB_OK"
+    assert _true_resid(olat, A, phi, x) <= 1.1 * TOL
+
+
+def test_cg_full_size_c1_fp64():
+    olat, lat, sigma, A, phi = _problem(1, 2048, 512)
+    hubtest.log_case("cg c1 full f64")
+    x, st = _solve(lat, sigma, phi, hub.cg_opts(hub.F64, max_iter=1000000))
+    assert st["status"] == "HUB_OK"
+    assert _true_resid(olat, A, phi, x) <= 1.1 * TOL
+
+
+def test_cg_full_size_c3_mixed_f16():
+    olat, lat, sigma, A, phi = _problem(3, 32, 256)
+    hubtest.log_case("cg c3 full f16")
+    x, st = _solve(lat, sigma, phi, hub.cg_opts(hub.F32, hub.F16))
+    assert st["status"] == "HUB_OK"
+    assert _true_resid(olat, A, phi, x) <= 1.1 * TOL
+
+
+# --- failure handling (all forced from the host; every kernel exits normally)
+
+def test_max_iter_reports_noconv_with_stats():
+    olat, lat, sigma, A, phi = _problem(1, 32, 64)
+    for opts in (hub.cg_opts(hub.F64, max_iter=1), hub.cg_opts(hub.F32, max_iter=7)):
+        x, st = _solve(lat, sigma, phi, opts, raise_on_noconv=False)
+        assert st["status"] == "HUB_E_NOCONV"
+        assert st["iters"] == opts.max_iter
+        r = _true_resid(olat, A, phi, x)
+        assert r == pytest.approx(st["true_rel_resid"], rel=1e-6)
+        assert r > TOL
+
+
+def test_nan_rhs_reports_noconv():
+    olat, lat, sigma, A, phi = _problem(1, 32, 64)
+    phi = phi.copy()
+    phi[17] = math.nan
+    x, st = _solve(lat, sigma, phi, hub.cg_opts(hub.F64), raise_on_noconv=False)
+    assert st["status"] == "HUB_E_NOCONV"
+
+
+def test_zero_rhs_converges_immediately():
+    olat, lat, sigma, A, phi = _problem(1, 32, 64)
+    x, st = _solve(lat, sigma, np.zeros_like(phi), hub.cg_opts(hub.F64))
+    assert st["status"] == "HUB_OK" and st["iters"] == 0 and not np.any(x)
+
+
+def test_singular_matrix_does_not_converge():
+    """t = 0, U = -40 (b = 3.57), nt = 2: on site 0 the field gives link factors
+    1 and -1, so prod_s l = -1 and det M = 0; a generic phi has a component
+    outside range(Q) and CG must report non-convergence."""
+    d, nx, nt = 1, 8, 2
+    lat = hub.lattice(d, nx, nt, 0.0, 0.05, -40.0, 0.0)
+    olat = oracle.Lattice(d, nx, nt, 0.0, 0.05, -40.0, 0.0)
+    b = oracle.hs_coupling(0.05, -40.0)
+    sigma = np.zeros(nx * nt)
+    sigma[0 + nx * 0] = math.asin(-2.0 / b)   # read by slice 1: l = -1
+    A = oracle.links(olat, sigma)
+    assert abs(A[0] * A[nx]) == pytest.approx(1.0)
+    phi = inputs.random_vector(nx * nt, 3)
+    x, st = _solve(lat, sigma, phi, hub.cg_opts(hub.F64, max_iter=500), raise_on_noconv=False)
+    assert st["status"] == "HUB_E_NOCONV"
+    assert st["true_rel_resid"] > 1e-3
+
+
+def test_repulsive_coupling_rejected():
+    lat = hub.lattice(1, 8, 8, U=1.0)
+    x = hubtest.empty(64, hub.F64)
+    with pytest.raises(hub.HubError) as e:
+        hub.hub_cg_solve(lat, x, x.clone(), hubtest.empty(64, hub.F64), hub.cg_opts())
+    assert e.value.status == hub.HUB_E_INVALID
