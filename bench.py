@@ -1,0 +1,233 @@
+"""Benchmark of the fermion-matrix hot path on one MI355X.
+
+One step is the d=1 2048 x 512 workload (1 048 576 sites, t=1, dtau=0.05,
+U=-2, sigma uniform, phi = M^T eta): links from sigma, phi = M^T eta, 1000
+bare hub_apply_MtM calls in FP64 cycling over 24 buffer sets (576 MiB, more
+than twice the 256 MiB Infinity Cache, so the sweeps stream from HBM), and
+one FP64 CG solve of M^T M x = phi to a true relative residual of 1e-10.
+
+Printed: one JSON line.  `value` is the effective HBM throughput of the bare
+sweeps (24 algorithmic bytes per site: read x and A, write z) over the timed
+steps.  `roofline` prices the sweep kernel's average duration, timed with
+HIP events around each launch, against the 8 TB/s HBM peak.  `detail` holds
+the CG solve rates (FP64 vs mixed precision on the d=3 workloads) and, with
+--serve, the served solves/s and latency percentiles.  `cpu_baseline` times
+the CPU oracle on a bounded sample of the same sweep on the host cores.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import statistics
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+SWEEP_BYTES_F64 = 24       # per site: x 8 + A 8 + z 8
+CG_ITER_BYTES_F64 = 80     # per site and iteration (phase A 56 + phase B 24)
+
+
+def _args():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--calls", type=int, default=1000, help="bare sweeps per step")
+    ap.add_argument("--sets", type=int, default=24, help="rotating buffer sets")
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--no-detail", action="store_true", help="skip the d=3 CG comparisons")
+    ap.add_argument("--serve", action="store_true", help="also run the serving workload")
+    ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--copy-calib", action="store_true",
+                    help="run one 256 MiB device copy (counter calibration)")
+    return ap.parse_args()
+
+
+def _build_if_missing():
+    from paper_1007_3432_amd import hub
+    if not os.path.exists(hub.LIB_PATH):
+        import __graft_entry__
+        __graft_entry__.build()
+
+
+def _dev(a, dtype=None):
+    import numpy as np
+    import torch
+    t = torch.from_numpy(np.ascontiguousarray(a)).to("cuda:0")
+    return t if dtype is None else t.to(dtype)
+
+
+def cg_compare(hub, inputs, shape, link_mixed, reps=1):
+    """FP64 CG vs mixed CG on one workload; solves/s and speedup."""
+    import torch
+    d, nx, nt = shape
+    lat = hub.lattice(d, nx, nt)
+    V = lat.volume
+    sigma, eta = inputs.sigma_eta(d, nx, nt, seed=0)
+    sig_d, eta_d = _dev(sigma), _dev(eta)
+    links = torch.empty(V, dtype=torch.float64, device="cuda:0")
+    hub.hub_links_from_sigma(lat, sig_d, links, hub.F64)
+    phi = torch.empty_like(eta_d)
+    hub.hub_apply_M(lat, links, hub.F64, hub.F64, eta_d, phi, 1)
+    out = {}
+    xs = {}
+    for name, opts in (("fp64", hub.cg_opts(hub.F64)),
+                       ("mixed", hub.cg_opts(hub.F32, link_mixed))):
+        x = torch.empty_like(phi)
+        hub.hub_cg_solve(lat, sig_d, phi, x, opts)           # warm-up
+        ms = []
+        for _ in range(reps):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            st = hub.hub_cg_solve(lat, sig_d, phi, x, opts)
+            torch.cuda.synchronize()
+            ms.append((time.perf_counter() - t0) * 1e3)
+        xs[name] = x
+        out[name] = {"ms_per_solve": min(ms), "solves_per_s": 1e3 / min(ms),
+                     "iters": st["iters"], "reliable_updates": st["reliable_updates"],
+                     "true_rel_resid": st["true_rel_resid"],
+                     "device_ms": st["ms"]}
+    out["mixed"]["link"] = {hub.F32: "f32", hub.F16: "f16_sin_sigma"}[link_mixed]
+    diff = (xs["mixed"] - xs["fp64"]).norm() / xs["fp64"].norm()
+    out["mixed"]["rel_diff_vs_fp64_solution"] = float(diff)
+    out["speedup_mixed_vs_fp64"] = out["fp64"]["ms_per_solve"] / out["mixed"]["ms_per_solve"]
+    return out
+
+
+def cpu_baseline(inputs, seconds: float):
+    """The CPU oracle's M^T M sweep on the host cores, same d=1 2048 x 512
+    workload, as many calls as fit in about `seconds`."""
+    import numpy as np
+    import oracle
+    cores = oracle.set_threads(os.cpu_count() or 1)
+    lat = oracle.Lattice(1, 2048, 512)
+    sigma, eta = inputs.sigma_eta(1, 2048, 512, seed=0)
+    A = oracle.links(lat, sigma)
+    x = np.ascontiguousarray(eta)
+    oracle.apply_MtM(lat, A, x)
+    n, t0 = 0, time.perf_counter()
+    while time.perf_counter() - t0 < seconds:
+        oracle.apply_MtM(lat, A, x)
+        n += 1
+    dt = time.perf_counter() - t0
+    gbs = SWEEP_BYTES_F64 * lat.volume * n / dt / 1e9
+    return {"value": gbs, "unit": "GB/s", "cores": cores, "kind": "oracle",
+            "sample": f"{n} oracle apply_MtM calls (FP64) on d=1 2048x512 "
+                      f"in {dt:.1f} s, same 24 B/site accounting",
+            "ms_per_call": dt / n * 1e3}
+
+
+def main():
+    a = _args()
+    if a.gpus != 1:
+        print(json.dumps({"error": "this benchmark runs on one GPU only; "
+                          f"--gpus {a.gpus} is not supported (single-GPU build)"}))
+        sys.exit(2)
+    _build_if_missing()
+    import numpy as np
+    import torch
+    from paper_1007_3432_amd import hub, inputs
+    hub.load()
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+
+    d, nx, nt = 1, 2048, 512
+    lat = hub.lattice(d, nx, nt)
+    V = lat.volume
+    sigma, eta = inputs.sigma_eta(d, nx, nt, seed=0)
+    sig_d, eta_d = _dev(sigma), _dev(eta)
+    nsets = a.sets
+    links = [torch.empty(V, dtype=torch.float64, device="cuda:0") for _ in range(nsets)]
+    xs = [_dev(inputs.random_vector(V, 100 + k)) for k in range(nsets)]
+    zs = [torch.empty(V, dtype=torch.float64, device="cuda:0") for _ in range(nsets)]
+    phi = torch.empty_like(eta_d)
+    x_cg = torch.empty_like(eta_d)
+    opts = hub.cg_opts(hub.F64, max_iter=1000000)
+
+    if a.copy_calib:
+        src = torch.empty(32 * 2 ** 20, dtype=torch.float64, device="cuda:0").fill_(1.0)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+
+    def step(timed: bool):
+        for k in range(nsets):
+            hub.hub_links_from_sigma(lat, sig_d, links[k], hub.F64)
+        hub.hub_apply_M(lat, links[0], hub.F64, hub.F64, eta_d, phi, 1)
+        ev = []
+        s0 = torch.cuda.Event(enable_timing=True)
+        s1 = torch.cuda.Event(enable_timing=True)
+        s0.record()
+        for c in range(a.calls):
+            k = c % nsets
+            if timed:
+                e0 = torch.cuda.Event(enable_timing=True)
+                e1 = torch.cuda.Event(enable_timing=True)
+                e0.record()
+            hub.hub_apply_MtM(lat, links[k], hub.F64, hub.F64, xs[k], zs[k])
+            if timed:
+                e1.record()
+                ev.append((e0, e1))
+        s1.record()
+        st = hub.hub_cg_solve(lat, sig_d, phi, x_cg, opts)
+        return s0, s1, ev, st
+
+    for _ in range(a.warmup):
+        step(False)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    recs = [step(True) for _ in range(a.steps)]
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+
+    sweep_ms = sum(s0.elapsed_time(s1) for s0, s1, _, _ in recs)
+    kern_ms = [e0.elapsed_time(e1) for _, _, ev, _ in recs for e0, e1 in ev]
+    avg_kern_s = statistics.mean(kern_ms) / 1e3
+    value = SWEEP_BYTES_F64 * V * a.calls * a.steps / (sweep_ms / 1e3) / 1e9
+    achieved = SWEEP_BYTES_F64 * V / avg_kern_s / 1e9
+    cg_stats = [r[3] for r in recs]
+    cg_ms = [s["ms"] for s in cg_stats]
+    cg_iters = cg_stats[-1]["iters"]
+    line = {
+        "metric": "MtM apply GB/s; CG solves/s FP64 vs mixed at 1e-10 resid; "
+                  "p50/p99 solve latency",
+        "value": value, "unit": "GB/s", "n_gpus": 1, "steps": a.steps,
+        "warmup": a.warmup, "ms_per_step": wall / a.steps * 1e3,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f64", "data": "synthetic",
+        "config": {"workload": "d=1 Nx=2048 x Nt=512 (1,048,576 sites): "
+                               f"{a.calls} FP64 hub_apply_MtM over {nsets} rotating "
+                               "buffer sets + 1 FP64 CG solve to 1e-10",
+                   "d": d, "nx": nx, "nt": nt, "t_hop": 1.0, "dtau": 0.05, "U": -2.0,
+                   "mu": 0.0, "parallelism": "single GPU"},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "kernel": "k_mtm_d1<OpApply<double>> (fused M^T M sweep)",
+                     "avg_launch_us": avg_kern_s * 1e6,
+                     "bytes_per_launch": SWEEP_BYTES_F64 * V},
+        "detail": {
+            "sweep_section_gbs_incl_launch_gaps": value,
+            "cg_fp64_c1": {"iters": cg_iters, "device_ms_per_solve": statistics.mean(cg_ms),
+                           "solves_per_s": 1e3 / statistics.mean(cg_ms),
+                           "true_rel_resid": cg_stats[-1]["true_rel_resid"],
+                           "effective_gbs": CG_ITER_BYTES_F64 * V * cg_iters
+                           / (statistics.mean(cg_ms) / 1e3) / 1e9},
+        },
+    }
+    if not a.no_detail:
+        line["detail"]["cg_c2_d3_16x160"] = cg_compare(hub, inputs, (3, 16, 160), hub.F32)
+        line["detail"]["cg_c3_d3_32x256"] = cg_compare(hub, inputs, (3, 32, 256), hub.F16)
+    if a.serve:
+        from paper_1007_3432_amd import serve_bench
+        line["detail"]["serve"] = serve_bench.run(hub, inputs)
+    if not a.no_cpu:
+        line["cpu_baseline"] = cpu_baseline(inputs, a.cpu_seconds)
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -104,7 +104,7 @@ def _load():
     lib.oracle_dot.argtypes = [ctypes.c_long, dp, dp]
     lib.oracle_dot.restype = ctypes.c_double
     lib.oracle_cg.argtypes = [lp, dp, dp, dp, ctypes.c_double, ctypes.c_int32,
-                              ctypes.POINTER(_CGResult)]
+                              ctypes.POINTER(_CGResult), dp, dp]
     lib.oracle_cg.restype = ctypes.c_int
     lib.oracle_set_threads.argtypes = [ctypes.c_int]
     lib.oracle_set_threads.restype = ctypes.c_int
@@ -175,15 +175,23 @@ def dot(a, b) -> float:
     return _load().oracle_dot(a.size, _ptr(a), _ptr(b))
 
 
-def cg(lat: Lattice, A, phi, tol: float = 1e-10, max_iter: int = 200000):
-    """Solve (M^T M) x = phi by CG from x0 = 0; returns (x, CGResult)."""
+def cg(lat: Lattice, A, phi, tol: float = 1e-10, max_iter: int = 200000,
+       record: bool = False):
+    """Solve (M^T M) x = phi by CG from x0 = 0; returns (x, CGResult), and
+    with record=True also (alphas, betas) of every iteration."""
     A = _vec(A, lat.volume)
     phi = _vec(phi, lat.volume)
     x = np.empty(lat.volume)
     res = _CGResult()
+    al = np.zeros(max_iter) if record else None
+    be = np.zeros(max_iter) if record else None
     rc = _load().oracle_cg(ctypes.byref(lat._c()), _ptr(A), _ptr(phi), _ptr(x),
-                           float(tol), int(max_iter), ctypes.byref(res))
+                           float(tol), int(max_iter), ctypes.byref(res),
+                           _ptr(al) if record else None, _ptr(be) if record else None)
     if rc < 0:
         raise MemoryError("oracle_cg: allocation failed")
-    return x, CGResult(res.iters, bool(res.converged), bool(res.breakdown),
-                       res.restarts, res.true_rel_resid, res.iter_rel_resid)
+    out = CGResult(res.iters, bool(res.converged), bool(res.breakdown),
+                   res.restarts, res.true_rel_resid, res.iter_rel_resid)
+    if record:
+        return x, out, (al[:res.iters], be[:max(res.iters - 1, 0)])
+    return x, out

@@ -172,10 +172,14 @@ double oracle_dot(long n, const double* a, const double* b) {
 }
 
 /* Conjugate gradient on Q x = phi, Q = M^T M, x0 = 0.  On exit x holds the
- * last iterate.  Work arrays are allocated here.  Returns 0 if converged,
- * 1 if max_iter was reached or CG broke down, -1 on allocation failure. */
+ * last iterate.  If alphas / betas are non-NULL (max_iter entries each) the
+ * step lengths alpha_k and coefficients beta_k of every iteration are
+ * recorded; they define the Lanczos tridiagonal of Q on the Krylov space.
+ * Work arrays are allocated here.  Returns 0 if converged, 1 if max_iter was
+ * reached or CG broke down, -1 on allocation failure. */
 int oracle_cg(const oracle_lattice* L, const double* A, const double* phi,
-              double* x, double tol, int32_t max_iter, oracle_cg_result* res) {
+              double* x, double tol, int32_t max_iter, oracle_cg_result* res,
+              double* alphas, double* betas) {
     long V = oracle_volume(L);
     double* r = (double*)malloc(sizeof(double) * V);
     double* p = (double*)malloc(sizeof(double) * V);
@@ -208,6 +212,7 @@ int oracle_cg(const oracle_lattice* L, const double* A, const double* phi,
             break;
         }
         double alpha = rho / pq;
+        if (alphas) alphas[k - 1] = alpha;
         for (long i = 0; i < V; ++i) x[i] += alpha * p[i];
         for (long i = 0; i < V; ++i) r[i] -= alpha * q[i];
         double rho_new = oracle_dot(V, r, r);
@@ -228,6 +233,7 @@ int oracle_cg(const oracle_lattice* L, const double* A, const double* phi,
             res->restarts += 1;
         }
         double beta = rho_new / rho;
+        if (betas) betas[k - 1] = beta;
         for (long i = 0; i < V; ++i) p[i] = r[i] + beta * p[i];
         rho = rho_new;
     }

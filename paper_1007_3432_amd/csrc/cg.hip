@@ -29,25 +29,29 @@ template <class RVec>
 __global__ __launch_bounds__(256) void k_init(CGScalars* sc, const double* __restrict__ phi,
                                               RVec* __restrict__ r, RVec* __restrict__ p0,
                                               double* __restrict__ x, float* __restrict__ xlo,
-                                              int V, double tol2, int max_iter,
-                                              double* partials) {
-    double part = 0.0;
+                                              int V, double tol2, double delta2,
+                                              int max_iter, double* partials) {
+    double part[1] = {0.0};
     for (int i = blockIdx.x * 256 + threadIdx.x; i < V; i += gridDim.x * 256) {
         const double f = phi[i];
         r[i] = (RVec)f;
         p0[i] = (RVec)0;
         x[i] = 0.0;
         if (xlo) xlo[i] = 0.0f;
-        part += f * f;
+        part[0] += f * f;
     }
-    double total;
-    if (grid_sum_last<256>(part, partials, &sc->ticket, total) && threadIdx.x == 0) {
+    double tot[1];
+    if (grid_sum_last<256, 1>(part, partials, &sc->ticket, tot) && threadIdx.x == 0) {
+        const double total = tot[0];
         sc->phi2 = total;
         sc->rho = total;
         sc->rho_prev = total;
         sc->rho_true = total;
+        sc->rho_ru = total;
+        sc->delta2 = delta2;
         sc->alpha = 0.0;
         sc->beta = 0.0;
+        sc->gamma = 1.0;
         sc->tol2phi2 = tol2 * total;
         sc->iter = 0;
         sc->max_iter = max_iter;
@@ -57,21 +61,24 @@ __global__ __launch_bounds__(256) void k_init(CGScalars* sc, const double* __res
     }
 }
 
-// r -= alpha q, rho' = r.r (FP64 accumulation).
+// r -= alpha q, rho' = r.r (FP64 accumulation).  Requests a true-residual
+// recompute when rho' meets tol or has dropped by delta^2 since the last
+// reliable update.
 template <class Vec>
 __global__ __launch_bounds__(256) void k_phaseB(CGScalars* sc, Vec* __restrict__ r,
                                                 const Vec* __restrict__ q, int V,
                                                 double* partials) {
     if (sc->done != kRunning) return;
     const Vec alpha = (Vec)sc->alpha;
-    double part = 0.0;
+    double part[1] = {0.0};
     for (int i = blockIdx.x * 256 + threadIdx.x; i < V; i += gridDim.x * 256) {
         const Vec rv = r[i] - alpha * q[i];
         r[i] = rv;
-        part += (double)rv * (double)rv;
+        part[0] += (double)rv * (double)rv;
     }
-    double total;
-    if (grid_sum_last<256>(part, partials, &sc->ticket, total) && threadIdx.x == 0) {
+    double tot[1];
+    if (grid_sum_last<256, 1>(part, partials, &sc->ticket, tot) && threadIdx.x == 0) {
+        const double total = tot[0];
         if (!std::isfinite(total)) {
             sc->done = kDoneBreakdown;
             return;
@@ -80,7 +87,7 @@ __global__ __launch_bounds__(256) void k_phaseB(CGScalars* sc, Vec* __restrict__
         sc->rho = total;
         sc->beta = total / sc->rho_prev;
         sc->iter += 1;
-        if (total <= sc->tol2phi2)
+        if (total <= sc->tol2phi2 || total < sc->delta2 * sc->rho_ru)
             sc->done = kDoneIterConverged;
         else if (sc->iter >= sc->max_iter)
             sc->done = kDoneMaxIter;
@@ -107,6 +114,11 @@ __global__ __launch_bounds__(256) void k_fold(CGScalars* sc, int mode, double* _
 }
 
 namespace {
+
+// Mixed solver: besides the fixed period, recompute the true residual once
+// the iterated one has dropped by this factor since the last recompute, so
+// that the FP32 recurrence never runs far ahead of the FP64 residual.
+constexpr double kReliableDelta = 0.1;
 
 // Pinned per-thread snapshot buffers and events for the chunk pipeline.
 struct HostCtx {
@@ -164,7 +176,7 @@ struct Solver {
 
     hub_status fold_and_residual(int mode) {
         k_fold<Vec><<<egrid, 256, 0, st>>>(sc, mode, x, xlo, p0, p1, g.V);
-        OpResidual<Vec> op{sc, x, phi, r, Link64{A64}, mode};
+        OpResidual<Vec> op{sc, x, phi, r, p0, p1, Link64{A64}, mode};
         return launch_q(g, P, op, yscratch, partials, &sc->ticket, st);
     }
 
@@ -198,7 +210,8 @@ hub_status run_solver(Solver<Vec, Lnk>& S, bool mixed, hub_cg_stats* out) {
     HUB_HIP(hipEventRecord(H.t0, st));
     k_zero_scalars<<<1, 64, 0, st>>>(S.sc);
     k_init<Vec><<<S.egrid, 256, 0, st>>>(S.sc, S.phi, S.r, S.p0, S.x, S.xlo, g.V,
-                                         o.tol * o.tol, o.max_iter, S.partials);
+                                         o.tol * o.tol, mixed ? kReliableDelta * kReliableDelta : 0.0,
+                                         o.max_iter, S.partials);
     HUB_HIP(hipGetLastError());
     const int C = mixed ? o.reliable_every : 50;
     // Every chunk either runs at least one iteration or ends the solve, so

@@ -28,10 +28,13 @@ struct CGScalars {
     double rho;        // current iterated r.r (FP64 accumulation)
     double rho_prev;   // r.r of the previous iteration
     double alpha;      // step length still to be added to x (0 once folded)
-    double beta;       // coefficient of the next p = r + beta p
+    double beta;       // p_new = gamma r + beta p_old
+    double gamma;      // 1 except right after a reliable update
     double phi2;       // |phi|^2
     double tol2phi2;   // tol^2 |phi|^2
     double rho_true;   // |phi - Q x|^2 of the last true-residual recompute
+    double rho_ru;     // r.r right after the last reliable update
+    double delta2;     // reliable update once rho < delta2 * rho_ru (0: never)
     double pq;         // last p.Qp
     int32_t iter;      // iterations completed
     int32_t max_iter;
@@ -43,7 +46,8 @@ struct CGScalars {
 
 enum : int32_t {
     kRunning = 0,
-    kDoneIterConverged = 1,  // iterated residual met tol: verify
+    kDoneIterConverged = 1,  // iterated residual met tol, or dropped by
+                             // delta since the last reliable update: recompute
     kDoneConverged = 2,      // true residual met tol
     kDoneBreakdown = 3,      // p.Qp <= 0 or a non-finite scalar
     kDoneMaxIter = 4,
@@ -100,18 +104,23 @@ __device__ inline double block_sum(double v) {
     return s;
 }
 
-// Single-pass grid reduction: every block deposits its sum, the block that
-// arrives last adds the deposits in block-id order (deterministic for a
-// given grid) and returns true with the total in `total` (valid in thread
-// 0).  The arrival counter is reset for the next launch.
-template <int BLOCK>
-__device__ inline bool grid_sum_last(double part, double* partials,
-                                     uint32_t* ticket, double& total) {
+// Single-pass grid reduction of NP values per thread: every block deposits
+// its sums, the block that arrives last adds the deposits in block-id order
+// (deterministic for a given grid) and returns true with the totals in
+// `total` (valid in thread 0).  The arrival counter is reset for the next
+// launch.  partials holds NP * gridDim.x doubles.
+template <int BLOCK, int NP>
+__device__ inline bool grid_sum_last(const double (&part)[NP], double* partials,
+                                     uint32_t* ticket, double (&total)[NP]) {
     __shared__ int am_last;
-    const double bs = block_sum<BLOCK>(part);
+    double bs[NP];
+#pragma unroll
+    for (int k = 0; k < NP; ++k) bs[k] = block_sum<BLOCK>(part[k]);
     if (threadIdx.x == 0) {
-        __hip_atomic_store(&partials[blockIdx.x], bs, __ATOMIC_RELAXED,
-                           __HIP_MEMORY_SCOPE_AGENT);
+#pragma unroll
+        for (int k = 0; k < NP; ++k)
+            __hip_atomic_store(&partials[NP * blockIdx.x + k], bs[k], __ATOMIC_RELAXED,
+                               __HIP_MEMORY_SCOPE_AGENT);
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
         const uint32_t prev = __hip_atomic_fetch_add(
             ticket, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
@@ -120,15 +129,19 @@ __device__ inline bool grid_sum_last(double part, double* partials,
     __syncthreads();
     if (!am_last) return false;
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-    double s = 0.0;
-    for (int k = threadIdx.x; k < (int)gridDim.x; k += BLOCK)
-        s += __hip_atomic_load(&partials[k], __ATOMIC_RELAXED,
-                               __HIP_MEMORY_SCOPE_AGENT);
-    total = block_sum<BLOCK>(s);
+#pragma unroll
+    for (int k = 0; k < NP; ++k) {
+        double s = 0.0;
+        for (int b = threadIdx.x; b < (int)gridDim.x; b += BLOCK)
+            s += __hip_atomic_load(&partials[NP * b + k], __ATOMIC_RELAXED,
+                                   __HIP_MEMORY_SCOPE_AGENT);
+        total[k] = block_sum<BLOCK>(s);
+    }
     if (threadIdx.x == 0)
         __hip_atomic_store(ticket, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     return true;
 }
+
 #endif
 
 }  // namespace hub

@@ -42,14 +42,14 @@ struct Link16 {
 // Ops.  Interface:
 //   acc_t, center_t          arithmetic type; per-site state kept from the
 //                            input read to the output write
-//   kReduce                  whether out() feeds a grid reduction
+//   kReduce, kNP             whether out() feeds a grid reduction of kNP sums
 //   skip()                   block-uniform early exit (device-side state)
 //   begin()                  per-thread set-up from device-side scalars
 //   link(i, s)               A at site i of slice s
 //   in(i)                    input vector value at any site
 //   in_center(i, c)          same, keeping what out() needs in c
-//   out(i, z, v, c, part)    consume z = (Q in)_i, v = in_i
-//   finish(total)            thread 0 of the last block: reduced total
+//   out(i, z, v, c, part)    consume z = (Q in)_i, v = in_i; add to part[]
+//   finish(total)            thread 0 of the last block: reduced totals
 // No op writes a buffer that in() reads, so tiles may run in any order.
 
 struct NoCenter {};
@@ -66,6 +66,7 @@ struct OpApply {
     using acc_t = Acc;
     using center_t = NoCenter;
     static constexpr bool kReduce = false;
+    static constexpr int kNP = 1;
     const Vec* x;
     Vec* z;
     Lnk lk;
@@ -74,21 +75,23 @@ struct OpApply {
     __device__ Acc link(int i, int s) const { return lk(i, s); }
     __device__ Acc in(int i) const { return (Acc)x[i]; }
     __device__ Acc in_center(int i, NoCenter&) const { return (Acc)x[i]; }
-    __device__ void out(int i, Acc zv, Acc, const NoCenter&, double&) const {
+    __device__ void out(int i, Acc zv, Acc, const NoCenter&, double (&)[kNP]) const {
         z[i] = (Vec)zv;
     }
-    __device__ void finish(double) const {}
+    __device__ void finish(const double (&)[kNP]) const {}
 };
 
 // CG direction update fused with q = Q p (Sec. 4.1, CG on Q):
-//   p_new = r + beta p_old,  q = Q p_new,  x += alpha_prev p_old,
-//   partial p_new . q  (FP64 accumulation)
+//   p_new = gamma r + beta p_old,  q = Q p_new,  x += alpha_prev p_old,
+//   partial p_new . q  (FP64 accumulation); gamma = 1 except right after a
+//   reliable update, where it removes the component of p along the new r.
 // p is double-buffered by iteration parity so halo reads never see a p_new.
 template <class Acc, class Vec, class XVec, class Lnk>
 struct OpPhaseA {
     using acc_t = Acc;
     struct center_t { Acc pold; };
     static constexpr bool kReduce = true;
+    static constexpr int kNP = 1;
     CGScalars* sc;
     const Vec* r;
     Vec* pbuf0;
@@ -99,7 +102,7 @@ struct OpPhaseA {
     // set by begin()
     const Vec* pold;
     Vec* pnew;
-    Acc beta, alpha;
+    Acc beta, alpha, gamma;
     __device__ bool skip() const { return sc->done != kRunning; }
     __device__ void begin() {
         const int it = sc->iter;
@@ -107,21 +110,24 @@ struct OpPhaseA {
         pnew = (it & 1) ? pbuf0 : pbuf1;
         beta = (Acc)sc->beta;
         alpha = (Acc)sc->alpha;
+        gamma = (Acc)sc->gamma;
     }
     __device__ Acc link(int i, int s) const { return lk(i, s); }
-    __device__ Acc in(int i) const { return (Acc)r[i] + beta * (Acc)pold[i]; }
+    __device__ Acc in(int i) const { return gamma * (Acc)r[i] + beta * (Acc)pold[i]; }
     __device__ Acc in_center(int i, center_t& c) const {
         c.pold = (Acc)pold[i];
-        return (Acc)r[i] + beta * c.pold;
+        return gamma * (Acc)r[i] + beta * c.pold;
     }
-    __device__ void out(int i, Acc zv, Acc v, const center_t& c, double& part) const {
+    __device__ void out(int i, Acc zv, Acc v, const center_t& c, double (&part)[kNP]) const {
         pnew[i] = (Vec)v;
         q[i] = (Vec)zv;
         x[i] = (XVec)((Acc)x[i] + alpha * c.pold);
-        part += (double)v * (double)zv;
+        part[0] += (double)v * (double)zv;
     }
-    __device__ void finish(double pq) const {
+    __device__ void finish(const double (&tot)[kNP]) const {
+        const double pq = tot[0];
         sc->pq = pq;
+        sc->gamma = 1.0;
         if (!(pq > 0.0) || !isfinite(pq)) {
             sc->done = kDoneBreakdown;
             sc->alpha = 0.0;  // alpha_prev was applied above
@@ -131,31 +137,40 @@ struct OpPhaseA {
     }
 };
 
-// FP64 true residual r = phi - Q x (Q with FP64 links), |r|^2 reduced.
-// The result replaces CG's residual (FP64, or rounded to FP32 in the mixed
-// solver) and decides convergence.
+// FP64 true residual r = phi - Q x (Q with FP64 links); reduces |r|^2 and
+// r.p.  The result replaces CG's residual (FP64, or rounded to FP32 in the
+// mixed solver) and decides convergence.  In the mixed solver (delta2 > 0)
+// the next direction is also made orthogonal to the new residual, the
+// reliable-update rule of Clark et al. (2010) for mixed-precision CG.
 template <class RVec>
 struct OpResidual {
     using acc_t = double;
     using center_t = NoCenter;
     static constexpr bool kReduce = true;
+    static constexpr int kNP = 2;
     CGScalars* sc;
     const double* x;
     const double* phi;
     RVec* r;
+    const RVec* pbuf0;
+    const RVec* pbuf1;
     Link64 lk;
     int mode;
+    const RVec* pcur;  // set by begin()
     __device__ bool skip() const { return !mode_runs(mode, sc->done); }
-    __device__ void begin() {}
+    __device__ void begin() { pcur = (sc->iter & 1) ? pbuf1 : pbuf0; }
     __device__ double link(int i, int s) const { return lk(i, s); }
     __device__ double in(int i) const { return x[i]; }
     __device__ double in_center(int i, NoCenter&) const { return x[i]; }
-    __device__ void out(int i, double zv, double, const NoCenter&, double& part) const {
+    __device__ void out(int i, double zv, double, const NoCenter&, double (&part)[kNP]) const {
         const double d = phi[i] - zv;
-        r[i] = (RVec)d;
-        part += d * d;
+        const RVec rd = (RVec)d;
+        r[i] = rd;
+        part[0] += d * d;
+        part[1] += (double)rd * (double)pcur[i];
     }
-    __device__ void finish(double rr) const {
+    __device__ void finish(const double (&tot)[kNP]) const {
+        const double rr = tot[0];
         sc->rho_true = rr;
         sc->alpha = 0.0;  // folded into x by the preceding fold kernel
         if (mode == kModeFinal) return;
@@ -168,8 +183,13 @@ struct OpResidual {
             sc->done = kDoneMaxIter;
         } else {
             // Continue from the true residual, keeping the direction p.
-            sc->beta = rr / sc->rho_prev;
+            const double beta = rr / sc->rho_prev;
+            double gamma = 1.0;
+            if (sc->delta2 > 0.0 && rr > 0.0) gamma = 1.0 - beta * (tot[1] / rr);
+            sc->beta = beta;
+            sc->gamma = gamma;
             sc->rho = rr;
+            sc->rho_ru = rr;
             sc->done = kRunning;
         }
     }
@@ -242,7 +262,7 @@ __global__ __launch_bounds__(TX) void k_mtm_d1(Geom g, Op op, int tiles_x,
     }
     __syncthreads();
 
-    double part = 0.0;
+    double part[Op::kNP] = {};
 #pragma unroll
     for (int rho = 0; rho < TT + 1; ++rho) {
         if (rho <= h) {
@@ -268,8 +288,8 @@ __global__ __launch_bounds__(TX) void k_mtm_d1(Geom g, Op op, int tiles_x,
         }
     }
     if constexpr (Op::kReduce) {
-        double total;
-        if (grid_sum_last<TX>(part, partials, ticket, total) && t == 0)
+        double total[Op::kNP];
+        if (grid_sum_last<TX, Op::kNP>(part, partials, ticket, total) && t == 0)
             op.finish(total);
     }
 }
@@ -311,7 +331,7 @@ __global__ __launch_bounds__(256) void k_gen_pass2(Geom g, Op op,
     if (op.skip()) return;
     op.begin();
     const int i = blockIdx.x * 256 + threadIdx.x;
-    double part = 0.0;
+    double part[Op::kNP] = {};
     if (i < g.V) {
         const int n = i % g.vs, s = i / g.vs;
         Acc hop = 0;
@@ -331,8 +351,8 @@ __global__ __launch_bounds__(256) void k_gen_pass2(Geom g, Op op,
         op.out(i, zv, v, c, part);
     }
     if constexpr (Op::kReduce) {
-        double total;
-        if (grid_sum_last<256>(part, partials, ticket, total) && threadIdx.x == 0)
+        double total[Op::kNP];
+        if (grid_sum_last<256, Op::kNP>(part, partials, ticket, total) && threadIdx.x == 0)
             op.finish(total);
     }
 }

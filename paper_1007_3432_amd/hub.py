@@ -85,6 +85,10 @@ def load():
     if not os.path.exists(LIB_PATH):
         raise RuntimeError(f"{LIB_PATH} is missing: build it first "
                            "(python -c 'import __graft_entry__ as g; g.build()')")
+    # torch brings its own HIP runtime (same soname, libamdhip64.so.7).  Load
+    # it first so that libhub binds to that one copy: two HIP runtimes in one
+    # process cannot share the device or each other's memory and streams.
+    import torch  # noqa: F401
     lib = ctypes.CDLL(LIB_PATH)
     vp, lp = ctypes.c_void_p, ctypes.POINTER(Lattice)
     lib.hub_links_from_sigma.argtypes = [lp, vp, vp, ctypes.c_int, vp]

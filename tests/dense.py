@@ -89,3 +89,17 @@ def plane_wave_lambdas(d, nx, nt, t_hop, dtau, f):
             w = np.pi * (2 * l + 1) / nt
             out.append((ms, l, a - f * np.exp(-1j * w)))
     return out
+
+
+def lanczos_condition(alphas, betas) -> float:
+    """cond(Q) estimated from the extreme eigenvalues of the Lanczos
+    tridiagonal that CG's coefficients define: T_kk = 1/alpha_k +
+    beta_{k-1}/alpha_{k-1}, T_{k,k+1} = sqrt(beta_k)/alpha_k."""
+    import scipy.linalg
+    a = np.asarray(alphas)
+    b = np.asarray(betas)[: a.size - 1]
+    diag = 1.0 / a
+    diag[1:] += b / a[:-1]
+    off = np.sqrt(b) / a[:-1]
+    ev = scipy.linalg.eigvalsh_tridiagonal(diag, off)
+    return float(ev[-1] / ev[0])

@@ -62,7 +62,9 @@ def test_links_parity(shape):
         out = hubtest.empty(lat.volume, link)
         hub.hub_links_from_sigma(lat, sig_d, out, link)
         got = out.double().cpu().numpy()
-        tol = 4e-16 if link == hub.F64 else 6e-8
+        # sin() may differ by 1 ulp between libm and the device library, and
+        # the device may contract 1 + b sin into an FMA: a few ulps in all.
+        tol = 1e-15 if link == hub.F64 else 1.2e-7
         assert np.max(np.abs(got - A_ref) / np.abs(A_ref)) <= tol
     out = hubtest.empty(lat.volume, hub.F16)
     hub.hub_links_from_sigma(lat, sig_d, out, hub.F16)

@@ -78,3 +78,17 @@ def test_cg_singular_M_does_not_converge():
     x, res = oracle.cg(lat, A, phi, tol=1e-10, max_iter=400)
     assert not res.converged
     assert res.true_rel_resid > 1e-3
+
+
+@pytest.mark.parametrize("d,nx,nt", [(1, 8, 16), (3, 3, 6), (1, 16, 24)])
+def test_lanczos_condition_matches_dense(d, nx, nt):
+    """The Ritz values of CG's Lanczos matrix approach the extreme eigenvalues
+    of Q: the condition estimate agrees with the dense spectrum."""
+    lat = Lattice(d, nx, nt)
+    sigma, eta = inputs.sigma_eta(d, nx, nt, seed=1)
+    A = oracle.links(lat, sigma)
+    phi = oracle.apply_Mt(lat, A, eta)
+    x, res, (al, be) = oracle.cg(lat, A, phi, tol=1e-12, record=True)
+    Q = dense.dense_from_apply(lambda v: oracle.apply_MtM(lat, A, v), lat.volume)
+    ev = np.linalg.eigvalsh(Q)
+    assert dense.lanczos_condition(al, be) == pytest.approx(ev[-1] / ev[0], rel=1e-3)
