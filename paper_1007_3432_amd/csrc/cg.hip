@@ -13,6 +13,7 @@
 // only after an iterated convergence in the FP64 solver.
 #include <cmath>
 
+#include "cgtiles.h"
 #include "sweep.h"
 
 namespace hub {
@@ -32,66 +33,25 @@ __global__ __launch_bounds__(256) void k_init(CGScalars* sc, const double* __res
                                               int V, double tol2, double delta2,
                                               int max_iter, double* partials) {
     double part[1] = {0.0};
-    for (int i = blockIdx.x * 256 + threadIdx.x; i < V; i += gridDim.x * 256) {
-        const double f = phi[i];
-        r[i] = (RVec)f;
-        p0[i] = (RVec)0;
-        x[i] = 0.0;
-        if (xlo) xlo[i] = 0.0f;
-        part[0] += f * f;
-    }
+    tile_init<RVec>(phi, r, p0, x, xlo, V, blockIdx.x, part);
     double tot[1];
-    if (grid_sum_last<256, 1>(part, partials, &sc->ticket, tot) && threadIdx.x == 0) {
-        const double total = tot[0];
-        sc->phi2 = total;
-        sc->rho = total;
-        sc->rho_prev = total;
-        sc->rho_true = total;
-        sc->rho_ru = total;
-        sc->delta2 = delta2;
-        sc->alpha = 0.0;
-        sc->beta = 0.0;
-        sc->gamma = 1.0;
-        sc->tol2phi2 = tol2 * total;
-        sc->iter = 0;
-        sc->max_iter = max_iter;
-        sc->reliable_updates = 0;
-        sc->done = !std::isfinite(total) ? kDoneBreakdown
-                                         : (total == 0.0 ? kDoneConverged : kRunning);
-    }
+    if (grid_sum_last<256, 1>(part, partials, blockIdx.x, gridDim.x, &sc->ticket, tot) &&
+        threadIdx.x == 0)
+        finish_init(sc, tot[0], tol2, delta2, max_iter);
 }
 
-// r -= alpha q, rho' = r.r (FP64 accumulation).  Requests a true-residual
-// recompute when rho' meets tol or has dropped by delta^2 since the last
-// reliable update.
+// r -= alpha q, rho' = r.r (FP64 accumulation).
 template <class Vec>
 __global__ __launch_bounds__(256) void k_phaseB(CGScalars* sc, Vec* __restrict__ r,
                                                 const Vec* __restrict__ q, int V,
                                                 double* partials) {
     if (sc->done != kRunning) return;
-    const Vec alpha = (Vec)sc->alpha;
     double part[1] = {0.0};
-    for (int i = blockIdx.x * 256 + threadIdx.x; i < V; i += gridDim.x * 256) {
-        const Vec rv = r[i] - alpha * q[i];
-        r[i] = rv;
-        part[0] += (double)rv * (double)rv;
-    }
+    tile_phaseB<Vec>(r, q, (Vec)sc->alpha, V, blockIdx.x, part);
     double tot[1];
-    if (grid_sum_last<256, 1>(part, partials, &sc->ticket, tot) && threadIdx.x == 0) {
-        const double total = tot[0];
-        if (!std::isfinite(total)) {
-            sc->done = kDoneBreakdown;
-            return;
-        }
-        sc->rho_prev = sc->rho;
-        sc->rho = total;
-        sc->beta = total / sc->rho_prev;
-        sc->iter += 1;
-        if (total <= sc->tol2phi2 || total < sc->delta2 * sc->rho_ru)
-            sc->done = kDoneIterConverged;
-        else if (sc->iter >= sc->max_iter)
-            sc->done = kDoneMaxIter;
-    }
+    if (grid_sum_last<256, 1>(part, partials, blockIdx.x, gridDim.x, &sc->ticket, tot) &&
+        threadIdx.x == 0)
+        finish_phaseB(sc, tot[0]);
 }
 
 // x += alpha p (+ x_lo, then x_lo = 0): the pending update, in FP64.
@@ -101,16 +61,7 @@ __global__ __launch_bounds__(256) void k_fold(CGScalars* sc, int mode, double* _
                                               const PVec* __restrict__ p0,
                                               const PVec* __restrict__ p1, int V) {
     if (!mode_runs(mode, sc->done)) return;
-    const double alpha = sc->alpha;
-    const PVec* p = (sc->iter & 1) ? p1 : p0;
-    for (int i = blockIdx.x * 256 + threadIdx.x; i < V; i += gridDim.x * 256) {
-        double v = x[i] + alpha * (double)p[i];
-        if (xlo) {
-            v += (double)xlo[i];
-            xlo[i] = 0.0f;
-        }
-        x[i] = v;
-    }
+    tile_fold<PVec>(x, xlo, (sc->iter & 1) ? p1 : p0, sc->alpha, V, blockIdx.x);
 }
 
 namespace {
@@ -162,7 +113,6 @@ struct Solver {
     const hub_cg_opts& o;
     hipStream_t st;
     SweepPlan P;
-    int egrid;
     // device buffers
     CGScalars* sc;
     double* partials;
@@ -175,7 +125,7 @@ struct Solver {
     double* yscratch;  // generic sweeps only (holds V doubles)
 
     hub_status fold_and_residual(int mode) {
-        k_fold<Vec><<<egrid, 256, 0, st>>>(sc, mode, x, xlo, p0, p1, g.V);
+        k_fold<Vec><<<elem_tiles(g.V), 256, 0, st>>>(sc, mode, x, xlo, p0, p1, g.V);
         OpResidual<Vec> op{sc, x, phi, r, p0, p1, Link64{A64}, mode};
         return launch_q(g, P, op, yscratch, partials, &sc->ticket, st);
     }
@@ -192,7 +142,7 @@ struct Solver {
         opA.lk = lk;
         for (int k = 0; k < iters; ++k) {
             HUB_TRY(launch_q(g, P, opA, (Vec*)yscratch, partials, &sc->ticket, st));
-            k_phaseB<Vec><<<egrid, 256, 0, st>>>(sc, r, q, g.V, partials);
+            k_phaseB<Vec><<<elem_tiles(g.V), 256, 0, st>>>(sc, r, q, g.V, partials);
         }
         HUB_TRY(fold_and_residual(mixed ? kModeReliable : kModeCheck));
         HUB_HIP(hipMemcpyAsync(snap, sc, sizeof(CGScalars), hipMemcpyDeviceToHost, st));
@@ -209,7 +159,7 @@ hub_status run_solver(Solver<Vec, Lnk>& S, bool mixed, hub_cg_stats* out) {
     HostCtx& H = g_ctx;
     HUB_HIP(hipEventRecord(H.t0, st));
     k_zero_scalars<<<1, 64, 0, st>>>(S.sc);
-    k_init<Vec><<<S.egrid, 256, 0, st>>>(S.sc, S.phi, S.r, S.p0, S.x, S.xlo, g.V,
+    k_init<Vec><<<elem_tiles(g.V), 256, 0, st>>>(S.sc, S.phi, S.r, S.p0, S.x, S.xlo, g.V,
                                          o.tol * o.tol, mixed ? kReliableDelta * kReliableDelta : 0.0,
                                          o.max_iter, S.partials);
     HUB_HIP(hipGetLastError());
@@ -288,7 +238,7 @@ hub_status cg_solve(const Geom& g, const double* sigma, const double* phi, doubl
     if (result == HUB_OK && mixed) result = launch_links(g, sigma, ws + o_lnk, o.link, st);
     if (result == HUB_OK) {
         if (!mixed) {
-            Solver<double, Link64> S{g, o, st, P, elementwise_grid(g)};
+            Solver<double, Link64> S{g, o, st, P};
             S.sc = (CGScalars*)(ws + o_sc);
             S.partials = (double*)(ws + o_part);
             S.phi = phi;
@@ -303,7 +253,7 @@ hub_status cg_solve(const Geom& g, const double* sigma, const double* phi, doubl
             S.yscratch = P.fused ? nullptr : (double*)(ws + o_y);
             result = run_solver(S, false, out);
         } else if (o.link == HUB_F32) {
-            Solver<float, Link32> S{g, o, st, P, elementwise_grid(g)};
+            Solver<float, Link32> S{g, o, st, P};
             S.sc = (CGScalars*)(ws + o_sc);
             S.partials = (double*)(ws + o_part);
             S.phi = phi;
@@ -318,7 +268,7 @@ hub_status cg_solve(const Geom& g, const double* sigma, const double* phi, doubl
             S.yscratch = P.fused ? nullptr : (double*)(ws + o_y);
             result = run_solver(S, true, out);
         } else {
-            Solver<float, Link16> S{g, o, st, P, elementwise_grid(g)};
+            Solver<float, Link16> S{g, o, st, P};
             S.sc = (CGScalars*)(ws + o_sc);
             S.partials = (double*)(ws + o_part);
             S.phi = phi;

@@ -104,14 +104,34 @@ __device__ inline double block_sum(double v) {
     return s;
 }
 
-// Single-pass grid reduction of NP values per thread: every block deposits
-// its sums, the block that arrives last adds the deposits in block-id order
-// (deterministic for a given grid) and returns true with the totals in
-// `total` (valid in thread 0).  The arrival counter is reset for the next
-// launch.  partials holds NP * gridDim.x doubles.
+// Sum of n deposits of NP values (deposit b at partials[NP*b + k]) in a
+// fixed order: thread t adds deposits t, t+BLOCK, ..., then the block tree.
+// Every caller that sums the same deposits gets the same bits.  Result in
+// thread 0.
 template <int BLOCK, int NP>
-__device__ inline bool grid_sum_last(const double (&part)[NP], double* partials,
-                                     uint32_t* ticket, double (&total)[NP]) {
+__device__ inline void reduce_deposits(const double* partials, int n, double (&total)[NP]) {
+#pragma unroll
+    for (int k = 0; k < NP; ++k) {
+        double s = 0.0;
+        for (int b = threadIdx.x; b < n; b += BLOCK)
+            s += __hip_atomic_load(&partials[NP * b + k], __ATOMIC_RELAXED,
+                                   __HIP_MEMORY_SCOPE_AGENT);
+        total[k] = block_sum<BLOCK>(s);
+    }
+}
+
+// Largest number of sums any reduction deposits per tile.
+constexpr int kMaxNP = 2;
+
+// Single-pass grid reduction of NP values per thread.  The block that owns
+// tile `slot` of `n` deposits its block sums; the block that arrives last
+// adds all deposits in tile order (reduce_deposits) and returns true with
+// the totals in `total` (valid in thread 0).  The arrival counter is reset
+// for the next launch.  partials holds NP * n doubles.
+template <int BLOCK, int NP>
+__device__ inline bool grid_sum_last(const double (&part)[NP], double* partials, int slot,
+                                     int n, uint32_t* ticket, double (&total)[NP]) {
+    static_assert(NP >= 1 && NP <= kMaxNP, "partials are sized for kMaxNP sums");
     __shared__ int am_last;
     double bs[NP];
 #pragma unroll
@@ -119,27 +139,35 @@ __device__ inline bool grid_sum_last(const double (&part)[NP], double* partials,
     if (threadIdx.x == 0) {
 #pragma unroll
         for (int k = 0; k < NP; ++k)
-            __hip_atomic_store(&partials[NP * blockIdx.x + k], bs[k], __ATOMIC_RELAXED,
+            __hip_atomic_store(&partials[NP * slot + k], bs[k], __ATOMIC_RELAXED,
                                __HIP_MEMORY_SCOPE_AGENT);
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
         const uint32_t prev = __hip_atomic_fetch_add(
             ticket, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
-        am_last = (prev == gridDim.x - 1);
+        am_last = (prev == (uint32_t)n - 1);
     }
     __syncthreads();
     if (!am_last) return false;
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-#pragma unroll
-    for (int k = 0; k < NP; ++k) {
-        double s = 0.0;
-        for (int b = threadIdx.x; b < (int)gridDim.x; b += BLOCK)
-            s += __hip_atomic_load(&partials[NP * b + k], __ATOMIC_RELAXED,
-                                   __HIP_MEMORY_SCOPE_AGENT);
-        total[k] = block_sum<BLOCK>(s);
-    }
+    reduce_deposits<BLOCK, NP>(partials, n, total);
     if (threadIdx.x == 0)
         __hip_atomic_store(ticket, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     return true;
+}
+
+// Block sums of one tile into deposit slot `slot` (no arrival counting): the
+// persistent serving kernel reduces them after a grid barrier.
+template <int BLOCK, int NP>
+__device__ inline void deposit(const double (&part)[NP], double* partials, int slot) {
+    double bs[NP];
+#pragma unroll
+    for (int k = 0; k < NP; ++k) bs[k] = block_sum<BLOCK>(part[k]);
+    if (threadIdx.x == 0) {
+#pragma unroll
+        for (int k = 0; k < NP; ++k)
+            __hip_atomic_store(&partials[NP * slot + k], bs[k], __ATOMIC_RELAXED,
+                               __HIP_MEMORY_SCOPE_AGENT);
+    }
 }
 
 #endif

@@ -205,17 +205,20 @@ struct OpResidual {
 // emits z = M^T y for slice s-1 as soon as y_s exists.  HBM traffic is the
 // input and A once (halo rows and columns are shared with neighbouring
 // tiles through L2) plus the outputs.
+template <int TX, int TT>
+constexpr int d1_lds_elems() { return (TT + 2) * (TX + 4) + 3 * (TX + 2); }
+
+// One tile b of the sweep (block of TX lanes); adds this lane's share of the
+// op's sums to part.  lds: d1_lds_elems<TX, TT>() elements.
 template <class Op, int TX, int TT>
-__global__ __launch_bounds__(TX) void k_mtm_d1(Geom g, Op op, int tiles_x,
-                                               double* partials, uint32_t* ticket) {
+__device__ __forceinline__ void tile_mtm_d1(const Geom& g, const Op& op, int tiles_x, int b,
+                                            typename Op::acc_t* lds,
+                                            double (&part)[Op::kNP]) {
     using Acc = typename Op::acc_t;
     using Center = typename Op::center_t;
-    __shared__ Acc xs[TT + 2][TX + 4];
-    __shared__ Acc ys[3][TX + 2];
-    if (op.skip()) return;
-    op.begin();
+    Acc (*xs)[TX + 4] = reinterpret_cast<Acc (*)[TX + 4]>(lds);
+    Acc (*ys)[TX + 2] = reinterpret_cast<Acc (*)[TX + 2]>(lds + (TT + 2) * (TX + 4));
     const int nx = g.nx, nt = g.nt;
-    const int b = xcd_remap(blockIdx.x, gridDim.x);
     const int tx = b % tiles_x, tt = b / tiles_x;
     const int n0 = tx * TX, s0 = tt * TT;
     const int w = min(TX, nx - n0), h = min(TT, nt - s0);
@@ -227,42 +230,55 @@ __global__ __launch_bounds__(TX) void k_mtm_d1(Geom g, Op op, int tiles_x,
     Acc cval[TT];
     Acc acen[TT + 1];
     Acc ahalo[TT + 1];
+    Acc xv[TT + 2];
+    Acc hv[TT + 2];
 
     // x halo lanes 0..3 fill LDS positions 0, 1, w+2, w+3.
     const int hpos = t < 2 ? t : w + t;
     const int hsite = wrap1(n0 - 2 + hpos, nx);
     // A halo lanes 0, 1 hold A at sites n0-1 and n0+w.
     const int asite = wrap1(t == 0 ? n0 - 1 : n0 + w, nx);
+    // Lanes past a ragged edge and rows past a ragged end re-read the last
+    // valid site / row, so that every load is unconditional and all of them
+    // are in flight together before the first LDS write.
+    const int tc = own ? t : w - 1;
 
 #pragma unroll
     for (int rho = 0; rho < TT + 2; ++rho) {
-        if (rho < h + 2) {
-            const int row = wrap1(s0 - 1 + rho, nt) * nx;
-            if (own) {
-                Acc v;
-                if (rho >= 1 && rho <= TT && rho <= h) {
-                    v = op.in_center(row + n0 + t, cen[rho - 1]);
-                    cval[rho - 1] = v;
-                } else {
-                    v = op.in(row + n0 + t);
-                }
-                xs[rho][t + 2] = v;
-            }
-            if (t < 4) xs[rho][hpos] = op.in(row + hsite);
-        }
+        const int row = wrap1(s0 - 1 + (rho < h + 2 ? rho : h + 1), nt) * nx;
+        if (rho >= 1 && rho <= TT)
+            xv[rho] = op.in_center(row + n0 + tc, cen[rho - 1]);
+        else
+            xv[rho] = op.in(row + n0 + tc);
     }
 #pragma unroll
     for (int rho = 0; rho < TT + 1; ++rho) {
-        if (rho <= h) {
-            const int s = wrap1(s0 + rho, nt);
-            const int row = s * nx;
-            if (own) acen[rho] = op.link(row + n0 + t, s);
-            if (t < 2) ahalo[rho] = op.link(row + asite, s);
+        const int s = wrap1(s0 + (rho <= h ? rho : h), nt);
+        acen[rho] = op.link(s * nx + n0 + tc, s);
+    }
+    if (t < 4) {
+#pragma unroll
+        for (int rho = 0; rho < TT + 2; ++rho) {
+            const int row = wrap1(s0 - 1 + (rho < h + 2 ? rho : h + 1), nt) * nx;
+            hv[rho] = op.in(row + hsite);
         }
     }
+    if (t < 2) {
+#pragma unroll
+        for (int rho = 0; rho < TT + 1; ++rho) {
+            const int s = wrap1(s0 + (rho <= h ? rho : h), nt);
+            ahalo[rho] = op.link(s * nx + asite, s);
+        }
+    }
+#pragma unroll
+    for (int rho = 0; rho < TT + 2; ++rho) {
+        if (own) xs[rho][t + 2] = xv[rho];
+        if (t < 4) xs[rho][hpos] = hv[rho];
+    }
+#pragma unroll
+    for (int rho = 0; rho < TT; ++rho) cval[rho] = xv[rho + 1];
     __syncthreads();
 
-    double part[Op::kNP] = {};
 #pragma unroll
     for (int rho = 0; rho < TT + 1; ++rho) {
         if (rho <= h) {
@@ -287,9 +303,228 @@ __global__ __launch_bounds__(TX) void k_mtm_d1(Geom g, Op op, int tiles_x,
             }
         }
     }
+}
+
+template <class Op, int TX, int TT>
+__global__ __launch_bounds__(TX) void k_mtm_d1(Geom g, Op op, int tiles_x,
+                                               double* partials, uint32_t* ticket) {
+    using Acc = typename Op::acc_t;
+    __shared__ Acc lds[d1_lds_elems<TX, TT>()];
+    if (op.skip()) return;
+    op.begin();
+    const int b = xcd_remap(blockIdx.x, gridDim.x);
+    double part[Op::kNP] = {};
+    tile_mtm_d1<Op, TX, TT>(g, op, tiles_x, b, lds, part);
     if constexpr (Op::kReduce) {
         double total[Op::kNP];
-        if (grid_sum_last<TX, Op::kNP>(part, partials, ticket, total) && t == 0)
+        if (grid_sum_last<TX, Op::kNP>(part, partials, b, gridDim.x, ticket, total) &&
+            threadIdx.x == 0)
+            op.finish(total);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Fused Q = M^T M sweep for d = 3, nx = NX.
+//
+// A block owns a tile of whole x rows (NX sites) times TY y-rows times TZ
+// z-planes and marches over a chunk of consecutive time slices.  At step s
+// it stages the input of slice s+1 on the tile plus a two-site halo in y and
+// z in LDS, forms y_{s+1} = W x_{s+1} + A_{s+1} x_s on the tile plus a
+// one-site halo (a 2-deep LDS ring holds y_s and y_{s+1}), and emits
+// z_s = W y_s + A_{s+1} y_{s+1} on the tile.  x is periodic inside a row, so
+// rows need no halo.  The tile's PZ = NX*TY*TZ sites are owned by fixed
+// lanes (site q by lane q mod 256), which keep their input value, op state
+// and A in registers from the load of slice s+1 to the output of slice s+1.
+template <int NX, int TY, int TZ>
+constexpr int d3_lds_elems() {
+    return NX * (TY + 4) * (TZ + 4) + 2 * NX * (TY + 2) * (TZ + 2);
+}
+
+// One tile b of the sweep (block of 256 lanes); adds this lane's share of
+// the op's sums to part.  lds: d3_lds_elems<NX, TY, TZ>() elements.
+template <class Op, int NX, int TY, int TZ>
+__device__ __forceinline__ void tile_mtm_d3(const Geom& g, const Op& op, int tiles_y,
+                                            int tiles_z, int tc, int b,
+                                            typename Op::acc_t* lds,
+                                            double (&part)[Op::kNP]) {
+    using Acc = typename Op::acc_t;
+    using Center = typename Op::center_t;
+    constexpr int XY = TY + 4, XZ = TZ + 4, YY = TY + 2, YZ = TZ + 2;
+    constexpr int PX = NX * XY * XZ, PY = NX * YY * YZ, PZ = NX * TY * TZ;
+    static_assert((NX & (NX - 1)) == 0, "NX must be a power of two");
+    static_assert(PZ % 256 == 0, "tile must be whole multiples of the block");
+    constexpr int NC = PZ / 256;
+    // Halo rows (y, z pairs outside the tile) of the X and Y stages.
+    constexpr int HRX = XY * XZ - TY * TZ, HRY = YY * YZ - TY * TZ;
+    constexpr int NHX = (NX * HRX + 255) / 256, NHY = (NX * HRY + 255) / 256;
+    Acc* X = lds;
+    Acc (*Y)[PY] = reinterpret_cast<Acc (*)[PY]>(lds + PX);
+    const int nt = g.nt, vs = g.vs;
+    const int iy = b % tiles_y;
+    b /= tiles_y;
+    const int iz = b % tiles_z;
+    const int ch = b / tiles_z;
+    const int y0 = iy * TY, z0 = iz * TZ, s0 = ch * tc;
+    const int h = min(tc, nt - s0);
+    const int t = threadIdx.x;
+    const Acc kappa = (Acc)g.kappa;
+
+    // Owned tile sites: spatial index, x coordinate, LDS index in X and Y.
+    int cn[NC], cx[NC], cxi[NC], cyi[NC];
+#pragma unroll
+    for (int k = 0; k < NC; ++k) {
+        const int q = t + 256 * k;
+        const int x = q % NX, r = q / NX, ty = r % TY, tz = r / TY;
+        cx[k] = x;
+        cn[k] = x + NX * ((y0 + ty) + NX * (z0 + tz));
+        cxi[k] = x + NX * ((ty + 2) + XY * (tz + 2));
+        cyi[k] = x + NX * ((ty + 1) + YY * (tz + 1));
+    }
+    // X halo positions of this lane: spatial index and X index.  Lanes past
+    // the end repeat the last position (loads stay unconditional; the LDS
+    // write is skipped).
+    int hxs[NHX], hxi[NHX];
+    bool hxo[NHX];
+#pragma unroll
+    for (int k = 0; k < NHX; ++k) {
+        int q = t + 256 * k;
+        hxo[k] = q < NX * HRX;
+        if (!hxo[k]) q = NX * HRX - 1;
+        const int x = q % NX, hr = q / NX;
+        int yx, zx;
+        if (hr < 2 * XY) {
+            zx = hr / XY;
+            yx = hr % XY;
+        } else if (hr < 4 * XY) {
+            zx = TZ + 2 + (hr - 2 * XY) / XY;
+            yx = (hr - 2 * XY) % XY;
+        } else {
+            const int r = hr - 4 * XY, c = r % 4;
+            zx = 2 + r / 4;
+            yx = c < 2 ? c : TY + c;
+        }
+        hxi[k] = x + NX * (yx + XY * zx);
+        hxs[k] = x + NX * (wrap1(y0 - 2 + yx, NX) + NX * wrap1(z0 - 2 + zx, NX));
+    }
+    // Y halo positions: spatial index, Y index, X index of the same site.
+    int hys[NHY], hyi[NHY], hyx[NHY], hyc[NHY];
+    bool hyo[NHY];
+#pragma unroll
+    for (int k = 0; k < NHY; ++k) {
+        int q = t + 256 * k;
+        hyo[k] = q < NX * HRY;
+        if (!hyo[k]) q = NX * HRY - 1;
+        const int x = q % NX, hr = q / NX;
+        int yy, zz;
+        if (hr < 2 * YY) {
+            zz = hr < YY ? 0 : TZ + 1;
+            yy = hr % YY;
+        } else {
+            const int r = hr - 2 * YY;
+            zz = 1 + r / 2;
+            yy = (r & 1) ? TY + 1 : 0;
+        }
+        hyc[k] = x;
+        hyi[k] = x + NX * (yy + YY * zz);
+        hyx[k] = x + NX * ((yy + 1) + XY * (zz + 1));
+        hys[k] = x + NX * (wrap1(y0 - 1 + yy, NX) + NX * wrap1(z0 - 1 + zz, NX));
+    }
+    // W applied to X around X index j (x coordinate x).
+    auto wx = [&](int x, int j) {
+        const int xm = (x - 1) & (NX - 1), xp = (x + 1) & (NX - 1);
+        return X[j] - kappa * (X[j - x + xm] + X[j - x + xp] + X[j - NX] + X[j + NX] +
+                               X[j - NX * XY] + X[j + NX * XY]);
+    };
+
+    Acc xc_cur[NC], xc_nxt[NC], ac[NC];
+    Center cc_cur[NC], cc_nxt[NC];
+    Acc xh[NHY], ah[NHY];
+
+    // Stage slice s: every global load first, then the LDS writes.
+    auto load_slice = [&](int s, Acc (&xc)[NC], Center (&cc)[NC]) {
+        const int off = vs * s;
+        Acc xv[NHX];
+#pragma unroll
+        for (int k = 0; k < NC; ++k) {
+            xc[k] = op.in_center(cn[k] + off, cc[k]);
+            ac[k] = op.link(cn[k] + off, s);
+        }
+#pragma unroll
+        for (int k = 0; k < NHX; ++k) xv[k] = op.in(hxs[k] + off);
+#pragma unroll
+        for (int k = 0; k < NHY; ++k) ah[k] = op.link(hys[k] + off, s);
+#pragma unroll
+        for (int k = 0; k < NC; ++k) X[cxi[k]] = xc[k];
+#pragma unroll
+        for (int k = 0; k < NHX; ++k)
+            if (hxo[k]) X[hxi[k]] = xv[k];
+    };
+    // y of the slice now in X into Y[buf]; xprev_c: previous slice at the
+    // owned sites; xh: previous slice at the halo positions (replaced by the
+    // current one).
+    auto form_y = [&](int buf, const Acc (&xprev_c)[NC]) {
+        Acc* Yb = Y[buf];
+#pragma unroll
+        for (int k = 0; k < NC; ++k)
+            Yb[cyi[k]] = wx(cx[k], cxi[k]) + ac[k] * xprev_c[k];
+#pragma unroll
+        for (int k = 0; k < NHY; ++k) {
+            const Acc v = wx(hyc[k], hyx[k]) + ah[k] * xh[k];
+            if (hyo[k]) Yb[hyi[k]] = v;
+            xh[k] = X[hyx[k]];
+        }
+    };
+
+    // Prologue: slice s0-1 at owned and halo positions, then y_{s0}.
+    {
+        const int offm = vs * wrap1(s0 - 1, nt);
+        Acc xp_c[NC];
+#pragma unroll
+        for (int k = 0; k < NC; ++k) xp_c[k] = op.in(cn[k] + offm);
+#pragma unroll
+        for (int k = 0; k < NHY; ++k) xh[k] = op.in(hys[k] + offm);
+        load_slice(s0, xc_cur, cc_cur);
+        __syncthreads();
+        form_y(0, xp_c);
+        __syncthreads();
+    }
+
+    for (int r = 0; r < h; ++r) {
+        const int s = s0 + r;
+        load_slice(wrap1(s + 1, nt), xc_nxt, cc_nxt);
+        __syncthreads();
+        form_y((r + 1) & 1, xc_cur);
+        __syncthreads();
+        const Acc* Yc = Y[r & 1];
+        const Acc* Yn = Y[(r + 1) & 1];
+#pragma unroll
+        for (int k = 0; k < NC; ++k) {
+            const int j = cyi[k], x = cx[k];
+            const int xm = (x - 1) & (NX - 1), xp = (x + 1) & (NX - 1);
+            const Acc zv = Yc[j] - kappa * (Yc[j - x + xm] + Yc[j - x + xp] + Yc[j - NX] +
+                                            Yc[j + NX] + Yc[j - NX * YY] + Yc[j + NX * YY]) +
+                           ac[k] * Yn[j];
+            op.out(cn[k] + vs * s, zv, xc_cur[k], cc_cur[k], part);
+            xc_cur[k] = xc_nxt[k];
+            cc_cur[k] = cc_nxt[k];
+        }
+    }
+}
+
+template <class Op, int NX, int TY, int TZ>
+__global__ __launch_bounds__(256) void k_mtm_d3(Geom g, Op op, int tiles_y, int tiles_z,
+                                                int tc, double* partials, uint32_t* ticket) {
+    using Acc = typename Op::acc_t;
+    __shared__ Acc lds[d3_lds_elems<NX, TY, TZ>()];
+    if (op.skip()) return;
+    op.begin();
+    const int b = xcd_remap(blockIdx.x, gridDim.x);
+    double part[Op::kNP] = {};
+    tile_mtm_d3<Op, NX, TY, TZ>(g, op, tiles_y, tiles_z, tc, b, lds, part);
+    if constexpr (Op::kReduce) {
+        double total[Op::kNP];
+        if (grid_sum_last<256, Op::kNP>(part, partials, b, gridDim.x, ticket, total) &&
+            threadIdx.x == 0)
             op.finish(total);
     }
 }
@@ -352,7 +587,8 @@ __global__ __launch_bounds__(256) void k_gen_pass2(Geom g, Op op,
     }
     if constexpr (Op::kReduce) {
         double total[Op::kNP];
-        if (grid_sum_last<256, Op::kNP>(part, partials, ticket, total) && threadIdx.x == 0)
+        if (grid_sum_last<256, Op::kNP>(part, partials, blockIdx.x, gridDim.x, ticket, total) &&
+            threadIdx.x == 0)
             op.finish(total);
     }
 }

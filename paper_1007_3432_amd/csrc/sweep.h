@@ -5,6 +5,7 @@
 #include <cstdlib>
 #include <cstring>
 
+#include "cgtiles.h"
 #include "internal.h"
 #include "stencil.h"
 
@@ -17,17 +18,31 @@ struct D1Shape { int tx, tt; };
 static constexpr D1Shape kD1Shapes[kD1_Count] = {
     {256, 8}, {128, 8}, {64, 8}, {256, 4}, {256, 16}, {128, 16}};
 
+// Tile shapes of the fused d = 3 kernel: whole rows of NX x TY x TZ.
+enum D3Tile { kD3_8x8x8 = 0, kD3_16x4x4, kD3_16x8x8, kD3_32x4x4, kD3_32x8x4, kD3_64x4x4,
+              kD3_Count };
+struct D3Shape { int nx, ty, tz; };
+static constexpr D3Shape kD3Shapes[kD3_Count] = {
+    {8, 8, 8}, {16, 4, 4}, {16, 8, 8}, {32, 4, 4}, {32, 8, 4}, {64, 4, 4}};
+
+enum SweepKind { kSweepD1 = 0, kSweepD3, kSweepGeneric };
+
 struct SweepPlan {
-    bool fused;
-    int variant;   // D1Tile when fused
-    int tiles_x;
+    int kind;      // SweepKind
+    bool fused;    // single pass (kSweepD1 / kSweepD3)
+    int variant;   // D1Tile or D3Tile
+    int tiles_x;   // d = 1
+    int tiles_y, tiles_z, tc;  // d = 3: tiles and slices per block
     int grid;      // blocks of the sweep kernel (pass 2 when generic)
 };
 
-// HUB_D1_TILE=<TX>x<TT> forces a d = 1 tile shape (tuning aid).
+// Tuning aids: HUB_D1_TILE=<TX>x<TT>, HUB_D3_TILE=<NX>x<TY>x<TZ>,
+// HUB_D3_TC=<slices per block>, HUB_SWEEP=generic.
+inline const char* env_or_null(const char* k) { return std::getenv(k); }
+
 inline int d1_tile_override() {
     static int v = [] {
-        const char* e = std::getenv("HUB_D1_TILE");
+        const char* e = env_or_null("HUB_D1_TILE");
         if (!e) return -1;
         for (int k = 0; k < kD1_Count; ++k) {
             char buf[32];
@@ -39,37 +54,84 @@ inline int d1_tile_override() {
     return v;
 }
 
+inline int d3_tile_override() {
+    static int v = [] {
+        const char* e = env_or_null("HUB_D3_TILE");
+        if (!e) return -1;
+        for (int k = 0; k < kD3_Count; ++k) {
+            char buf[32];
+            std::snprintf(buf, sizeof(buf), "%dx%dx%d", kD3Shapes[k].nx, kD3Shapes[k].ty,
+                          kD3Shapes[k].tz);
+            if (std::strcmp(buf, e) == 0) return k;
+        }
+        return -1;
+    }();
+    return v;
+}
+
+inline int env_int(const char* k, int dflt) {
+    const char* e = env_or_null(k);
+    return e ? std::atoi(e) : dflt;
+}
+
+inline bool force_generic() {
+    static bool v = [] {
+        const char* e = env_or_null("HUB_SWEEP");
+        return e && std::strcmp(e, "generic") == 0;
+    }();
+    return v;
+}
+
 inline SweepPlan plan_sweep(const Geom& g) {
     SweepPlan p{};
-    if (g.d == 1) {
+    p.kind = kSweepGeneric;
+    p.variant = -1;
+    if (!force_generic() && g.d == 1) {
         int v = d1_tile_override();
         if (v < 0) v = g.nx >= 256 ? kD1_256x8 : (g.nx >= 128 ? kD1_128x8 : kD1_64x8);
-        p.fused = true;
+        p.kind = kSweepD1;
         p.variant = v;
         p.tiles_x = ceil_div(g.nx, kD1Shapes[v].tx);
         p.grid = p.tiles_x * ceil_div(g.nt, kD1Shapes[v].tt);
-    } else {
-        p.fused = false;
-        p.variant = -1;
-        p.tiles_x = 0;
-        p.grid = ceil_div(g.V, 256);
+    } else if (!force_generic() && g.d == 3) {
+        int v = d3_tile_override();
+        if (v >= 0 && kD3Shapes[v].nx != g.nx) v = -1;
+        if (v < 0) {
+            switch (g.nx) {
+                case 8: v = kD3_8x8x8; break;
+                case 16: v = kD3_16x4x4; break;
+                case 32: v = kD3_32x4x4; break;
+                case 64: v = kD3_64x4x4; break;
+                default: v = -1;
+            }
+        }
+        if (v >= 0) {
+            const D3Shape sh = kD3Shapes[v];
+            p.kind = kSweepD3;
+            p.variant = v;
+            p.tiles_y = g.nx / sh.ty;
+            p.tiles_z = g.nx / sh.tz;
+            const int tiles = p.tiles_y * p.tiles_z;
+            // Aim at ~2048 blocks; longer marches amortise the prologue slice.
+            int tc = ceil_div(g.nt * tiles, 2048);
+            tc = tc < 2 ? 2 : (tc > 32 ? 32 : tc);
+            tc = env_int("HUB_D3_TC", tc);
+            if (tc < 1) tc = 1;
+            p.tc = tc;
+            p.grid = tiles * ceil_div(g.nt, tc);
+        }
     }
+    if (p.kind == kSweepGeneric) p.grid = ceil_div(g.V, 256);
+    p.fused = p.kind != kSweepGeneric;
     return p;
 }
 
-// Blocks of the grid-stride elementwise kernels: a function of V only, so
-// that reductions are summed in the same order on every call.
-inline int elementwise_grid(const Geom& g) {
-    int b = ceil_div(g.V, 256 * 4);
-    return b < 1 ? 1 : (b > 2048 ? 2048 : b);
-}
-
-// Deposit slots any reduction over this geometry may need.
+// Doubles of deposit space any reduction over this geometry may need:
+// kMaxNP sums for each tile of the largest grid (sweep or element-wise).
 inline int max_partials(const Geom& g) {
     const SweepPlan p = plan_sweep(g);
-    int m = p.grid;
-    const int e = elementwise_grid(g);
-    return m > e ? m : e;
+    const int e = elem_tiles(g.V);
+    return kMaxNP * (p.grid > e ? p.grid : e);
 }
 
 // One sweep: z = Q in, consumed by op.out().  y: scratch of g.V acc_t
@@ -78,7 +140,7 @@ template <class Op>
 hub_status launch_q(const Geom& g, const SweepPlan& P, const Op& op,
                     typename Op::acc_t* y, double* partials, uint32_t* ticket,
                     hipStream_t st) {
-    if (P.fused) {
+    if (P.kind == kSweepD1) {
         switch (P.variant) {
 #define HUB_D1_CASE(K, TX, TT)                                                   \
     case K:                                                                      \
@@ -93,7 +155,26 @@ hub_status launch_q(const Geom& g, const SweepPlan& P, const Op& op,
             HUB_D1_CASE(kD1_128x16, 128, 16)
 #undef HUB_D1_CASE
             default:
-                return set_error(HUB_E_INVALID, "internal: bad tile variant");
+                return set_error(HUB_E_INVALID, "internal: bad d=1 tile variant");
+        }
+    } else if (P.kind == kSweepD3) {
+        if (g.nx != kD3Shapes[P.variant].nx)
+            return set_error(HUB_E_INVALID, "internal: d=3 tile does not fit nx");
+        switch (P.variant) {
+#define HUB_D3_CASE(K, NX, TY, TZ)                                                  \
+    case K:                                                                         \
+        k_mtm_d3<Op, NX, TY, TZ><<<P.grid, 256, 0, st>>>(g, op, P.tiles_y, P.tiles_z, \
+                                                          P.tc, partials, ticket);   \
+        break;
+            HUB_D3_CASE(kD3_8x8x8, 8, 8, 8)
+            HUB_D3_CASE(kD3_16x4x4, 16, 4, 4)
+            HUB_D3_CASE(kD3_16x8x8, 16, 8, 8)
+            HUB_D3_CASE(kD3_32x4x4, 32, 4, 4)
+            HUB_D3_CASE(kD3_32x8x4, 32, 8, 4)
+            HUB_D3_CASE(kD3_64x4x4, 64, 4, 4)
+#undef HUB_D3_CASE
+            default:
+                return set_error(HUB_E_INVALID, "internal: bad d=3 tile variant");
         }
     } else {
         if (!y) return set_error(HUB_E_INVALID, "internal: generic sweep needs scratch");
