@@ -17,10 +17,13 @@ OUT = os.path.join(HERE, "_build")
 LIB = os.path.join(OUT, "libhub.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
-SOURCES = ["apply.hip", "mtm.hip", "cg.hip", "serve.cpp", "capi.cpp"]
+SOURCES = ["apply.hip", "mtm.hip", "cg.hip", "serve.hip", "capi.cpp"]
 
 CFLAGS = [
     "-x", "hip", "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
+    # Contract a*b+c into an FMA only within one expression, so that a given
+    # source line rounds the same wherever it is inlined.
+    "-ffp-contract=on",
     "-fvisibility=hidden", "-Wall", "-Wno-unused-function",
     # Packed FP32 arithmetic stays off: the compiler only emits scalar FP32.
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",

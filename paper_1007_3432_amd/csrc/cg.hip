@@ -292,4 +292,28 @@ hub_status cg_solve(const Geom& g, const double* sigma, const double* phi, doubl
     return result;
 }
 
+// ---------------------------------------------------------------------------
+// Set-up and wrap-up of one solve of the serving kernel: the same kernels the
+// one-solve path runs before its first and after its last chunk.
+
+double reliable_delta() { return kReliableDelta; }
+
+hub_status serve_slot_init(const Geom& g, CGScalars* sc, const double* phi, float* r, float* p0,
+                           double* x, float* xlo, double tol2, double delta2, int max_iter,
+                           double* partials, hipStream_t st) {
+    k_zero_scalars<<<1, 64, 0, st>>>(sc);
+    k_init<float><<<elem_tiles(g.V), 256, 0, st>>>(sc, phi, r, p0, x, xlo, g.V, tol2, delta2,
+                                                   max_iter, partials);
+    HUB_HIP(hipGetLastError());
+    return HUB_OK;
+}
+
+hub_status serve_slot_final(const Geom& g, const SweepPlan& P, CGScalars* sc, const double* phi,
+                            double* x, float* xlo, float* r, float* p0, float* p1,
+                            const double* A64, double* partials, hipStream_t st) {
+    k_fold<float><<<elem_tiles(g.V), 256, 0, st>>>(sc, kModeFinal, x, xlo, p0, p1, g.V);
+    OpResidual<float> op{sc, x, phi, r, p0, p1, Link64{A64}, kModeFinal};
+    return launch_q(g, P, op, nullptr, partials, &sc->ticket, st);
+}
+
 }  // namespace hub
