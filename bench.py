@@ -42,6 +42,8 @@ def _args():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-detail", action="store_true", help="skip the d=3 CG comparisons")
     ap.add_argument("--serve", action="store_true", help="also run the serving workload")
+    ap.add_argument("--engine", type=int, default=0, help="serving engine: 0 batched, 1 persistent")
+    ap.add_argument("--serve-seconds", type=float, default=15.0)
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--copy-calib", action="store_true",
                     help="run one 256 MiB device copy (counter calibration)")
@@ -97,6 +99,87 @@ def cg_compare(hub, inputs, shape, link_mixed, reps=1):
     out["mixed"]["rel_diff_vs_fp64_solution"] = float(diff)
     out["speedup_mixed_vs_fp64"] = out["fp64"]["ms_per_solve"] / out["mixed"]["ms_per_solve"]
     return out
+
+
+def serve_bench(hub, inputs, engine: int, seconds: float, think_mean_s: float | None,
+                n_chains: int = 64):
+    """Serving workload: n_chains HMC chains on the four lattice shapes, each
+    issuing one mixed-precision solve at a time.  With think_mean_s, a chain
+    waits an exponential think time after each completion (aggregate Poisson
+    arrivals at n_chains / think_mean_s per second while the system keeps
+    up); with None every chain resubmits at once (capacity).  Latency is
+    submit -> result visible to poll."""
+    import numpy as np
+    import torch
+    opts = hub.cg_opts(hub.F32, hub.F32, tol=1e-10, max_iter=200000, reliable_every=50)
+    srv = hub.Server(hbm_budget_bytes=64 << 30, max_inflight=n_chains, cg=opts, engine=engine)
+    rng = np.random.default_rng(7)
+    chains = []
+    for c in range(n_chains):
+        d, nx, nt = inputs.chain_shape(c)
+        lat = hub.lattice(d, nx, nt)
+        sigma = inputs.chain_sigma(c)
+        sig_d = torch.from_numpy(sigma).cuda()
+        links = torch.empty(lat.volume, dtype=torch.float64, device="cuda")
+        hub.hub_links_from_sigma(lat, sig_d, links, hub.F64)
+        phis = []
+        for k in range(2):
+            eta = torch.from_numpy(inputs.chain_eta(c, k)).cuda()
+            phi = torch.empty_like(eta)
+            hub.hub_apply_M(lat, links, hub.F64, hub.F64, eta, phi, 1)
+            phis.append(phi.cpu().numpy())
+        chains.append({"lat": lat, "sigma": sigma, "phis": phis, "sent_sigma": False,
+                       "ticket": None, "t_submit": 0.0, "next_at": 0.0, "k": 0})
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for ch in chains:
+        ch["next_at"] = t0 + (rng.exponential(think_mean_s) if think_mean_s else 0.0)
+    lat_ms, iters, done_t = [], [], []
+    shapes = {}
+    while True:
+        now = time.perf_counter()
+        if now - t0 > seconds:
+            break
+        for c, ch in enumerate(chains):
+            if ch["ticket"] is None and now >= ch["next_at"]:
+                sig = None if ch["sent_sigma"] else ch["sigma"]
+                ch["ticket"] = srv.submit(c, ch["lat"], sig, ch["phis"][ch["k"] % 2])
+                ch["sent_sigma"] = True
+                ch["t_submit"] = time.perf_counter()
+                ch["k"] += 1
+            elif ch["ticket"] is not None:
+                r = srv.poll(ch["ticket"], ch["lat"].volume)
+                if r is not None:
+                    t = time.perf_counter()
+                    lat_ms.append((t - ch["t_submit"]) * 1e3)
+                    iters.append(r[1]["iters"])
+                    done_t.append(t - t0)
+                    key = "d%d_%dx%d" % (ch["lat"].d, ch["lat"].nx, ch["lat"].nt)
+                    shapes[key] = shapes.get(key, 0) + 1
+                    assert r[1]["status"] == "HUB_OK", r[1]
+                    ch["ticket"] = None
+                    ch["next_at"] = t + (rng.exponential(think_mean_s) if think_mean_s else 0.0)
+        time.sleep(0.0005)
+    # drain
+    for ch in chains:
+        while ch["ticket"] is not None:
+            if srv.poll(ch["ticket"], ch["lat"].volume) is not None:
+                ch["ticket"] = None
+            else:
+                time.sleep(0.001)
+    srv.close()
+    # steady state: skip the first 20% of the run
+    warm = 0.2 * seconds
+    keep = [i for i, t in enumerate(done_t) if t >= warm]
+    lat_keep = np.array([lat_ms[i] for i in keep]) if keep else np.array(lat_ms)
+    rate = len(keep) / (seconds - warm) if keep else len(done_t) / seconds
+    return {"engine": "persistent" if engine == 1 else "batched",
+            "chains": n_chains, "offered_per_s": (n_chains / think_mean_s) if think_mean_s else None,
+            "solves_per_s": rate, "completed": len(done_t),
+            "p50_latency_ms": float(np.percentile(lat_keep, 50)) if lat_keep.size else None,
+            "p99_latency_ms": float(np.percentile(lat_keep, 99)) if lat_keep.size else None,
+            "mean_iters": float(np.mean(iters)) if iters else None, "by_shape": shapes,
+            "seconds": seconds}
 
 
 def cpu_baseline(inputs, seconds: float):
@@ -222,8 +305,10 @@ def main():
         line["detail"]["cg_c2_d3_16x160"] = cg_compare(hub, inputs, (3, 16, 160), hub.F32)
         line["detail"]["cg_c3_d3_32x256"] = cg_compare(hub, inputs, (3, 32, 256), hub.F16)
     if a.serve:
-        from paper_1007_3432_amd import serve_bench
-        line["detail"]["serve"] = serve_bench.run(hub, inputs)
+        line["detail"]["serve_poisson_200_per_s"] = serve_bench(hub, inputs, a.engine,
+                                                               a.serve_seconds, 64 / 200)
+        line["detail"]["serve_capacity"] = serve_bench(hub, inputs, a.engine,
+                                                       a.serve_seconds, None)
     if not a.no_cpu:
         line["cpu_baseline"] = cpu_baseline(inputs, a.cpu_seconds)
     print(json.dumps(line), flush=True)

@@ -135,15 +135,22 @@ HUB_API hub_status hub_cg_solve(const hub_lattice* lat, const double* sigma,
  * A server owns one worker thread, one HIP stream and the resident state of
  * every chain it has seen (field, links, Krylov vectors).  Requests are
  * admitted while their footprint fits hbm_budget_bytes and a slot is free;
- * admitted solves step together in one persistent device kernel, newly
- * admitted ones join between epochs, finished ones leave. */
+ * admitted solves step together on the device (all in-flight solves in each
+ * launch, or in one persistent kernel), newly
+ * admitted ones join between epochs (reliable_every iterations plus the
+ * reliable update), finished ones leave.  Every solve takes exactly the
+ * steps of hub_cg_solve with the same options, so its result is the same
+ * alone and in the mix. */
 typedef struct hub_server hub_server;
 
 typedef struct {
     size_t hbm_budget_bytes; /* cap on resident chain + solve memory */
     int32_t max_inflight;    /* cap on concurrently stepped solves, >= 1 */
-    int32_t reserved;
-    hub_cg_opts cg;          /* solver options for every request */
+    int32_t engine;          /* 0: one launch per CG phase for all in-flight
+                                solves, kernel boundaries as the device-wide
+                                sync (default); 1: one persistent cooperative
+                                kernel per epoch with grid barriers */
+    hub_cg_opts cg;          /* solver options (bulk must be HUB_F32) */
 } hub_serve_opts;
 
 HUB_API hub_status hub_serve_create(const hub_serve_opts* opts, hub_server** out);

@@ -25,33 +25,42 @@ __global__ void k_zero_scalars(CGScalars* sc) {
     for (int k = threadIdx.x; k < (int)(sizeof(CGScalars) / 4); k += blockDim.x) w[k] = 0;
 }
 
-// r = phi, p = 0, x = 0 (x_lo = 0), |phi|^2.
+// r = phi, p = 0, x = 0 (x_lo = 0), |phi|^2 (deposits; k_init_finish).
 template <class RVec>
-__global__ __launch_bounds__(256) void k_init(CGScalars* sc, const double* __restrict__ phi,
+__global__ __launch_bounds__(256) void k_init(const double* __restrict__ phi,
                                               RVec* __restrict__ r, RVec* __restrict__ p0,
                                               double* __restrict__ x, float* __restrict__ xlo,
-                                              int V, double tol2, double delta2,
-                                              int max_iter, double* partials) {
+                                              int V, double* partials) {
     double part[1] = {0.0};
     tile_init<RVec>(phi, r, p0, x, xlo, V, blockIdx.x, part);
-    double tot[1];
-    if (grid_sum_last<256, 1>(part, partials, blockIdx.x, gridDim.x, &sc->ticket, tot) &&
-        threadIdx.x == 0)
-        finish_init(sc, tot[0], tol2, delta2, max_iter);
+    deposit<256, 1>(part, partials, blockIdx.x);
 }
 
-// r -= alpha q, rho' = r.r (FP64 accumulation).
+__global__ __launch_bounds__(256) void k_init_finish(CGScalars* sc, const double* partials,
+                                                     int n, double tol2, double delta2,
+                                                     int max_iter) {
+    double tot[1];
+    reduce_deposits<256, 1>(partials, n, tot);
+    if (threadIdx.x == 0) finish_init(sc, tot[0], tol2, delta2, max_iter);
+}
+
+// r -= alpha q, r.r (deposits; k_phaseB_finish).
 template <class Vec>
-__global__ __launch_bounds__(256) void k_phaseB(CGScalars* sc, Vec* __restrict__ r,
+__global__ __launch_bounds__(256) void k_phaseB(const CGScalars* sc, Vec* __restrict__ r,
                                                 const Vec* __restrict__ q, int V,
                                                 double* partials) {
     if (sc->done != kRunning) return;
     double part[1] = {0.0};
     tile_phaseB<Vec>(r, q, (Vec)sc->alpha, V, blockIdx.x, part);
+    deposit<256, 1>(part, partials, blockIdx.x);
+}
+
+__global__ __launch_bounds__(256) void k_phaseB_finish(CGScalars* sc, const double* partials,
+                                                       int n) {
+    if (sc->done != kRunning) return;
     double tot[1];
-    if (grid_sum_last<256, 1>(part, partials, blockIdx.x, gridDim.x, &sc->ticket, tot) &&
-        threadIdx.x == 0)
-        finish_phaseB(sc, tot[0]);
+    reduce_deposits<256, 1>(partials, n, tot);
+    if (threadIdx.x == 0) finish_phaseB(sc, tot[0]);
 }
 
 // x += alpha p (+ x_lo, then x_lo = 0): the pending update, in FP64.
@@ -127,7 +136,7 @@ struct Solver {
     hub_status fold_and_residual(int mode) {
         k_fold<Vec><<<elem_tiles(g.V), 256, 0, st>>>(sc, mode, x, xlo, p0, p1, g.V);
         OpResidual<Vec> op{sc, x, phi, r, p0, p1, Link64{A64}, mode};
-        return launch_q(g, P, op, yscratch, partials, &sc->ticket, st);
+        return launch_q(g, P, op, yscratch, partials, st);
     }
 
     hub_status chunk(int iters, CGScalars* snap, hipEvent_t ev, bool mixed) {
@@ -141,8 +150,9 @@ struct Solver {
         if constexpr (sizeof(Vec) == 8) opA.x = x; else opA.x = xlo;
         opA.lk = lk;
         for (int k = 0; k < iters; ++k) {
-            HUB_TRY(launch_q(g, P, opA, (Vec*)yscratch, partials, &sc->ticket, st));
+            HUB_TRY(launch_q(g, P, opA, (Vec*)yscratch, partials, st));
             k_phaseB<Vec><<<elem_tiles(g.V), 256, 0, st>>>(sc, r, q, g.V, partials);
+            k_phaseB_finish<<<1, 256, 0, st>>>(sc, partials, elem_tiles(g.V));
         }
         HUB_TRY(fold_and_residual(mixed ? kModeReliable : kModeCheck));
         HUB_HIP(hipMemcpyAsync(snap, sc, sizeof(CGScalars), hipMemcpyDeviceToHost, st));
@@ -159,9 +169,9 @@ hub_status run_solver(Solver<Vec, Lnk>& S, bool mixed, hub_cg_stats* out) {
     HostCtx& H = g_ctx;
     HUB_HIP(hipEventRecord(H.t0, st));
     k_zero_scalars<<<1, 64, 0, st>>>(S.sc);
-    k_init<Vec><<<elem_tiles(g.V), 256, 0, st>>>(S.sc, S.phi, S.r, S.p0, S.x, S.xlo, g.V,
-                                         o.tol * o.tol, mixed ? kReliableDelta * kReliableDelta : 0.0,
-                                         o.max_iter, S.partials);
+    k_init<Vec><<<elem_tiles(g.V), 256, 0, st>>>(S.phi, S.r, S.p0, S.x, S.xlo, g.V, S.partials);
+    k_init_finish<<<1, 256, 0, st>>>(S.sc, S.partials, elem_tiles(g.V), o.tol * o.tol,
+                                     mixed ? kReliableDelta * kReliableDelta : 0.0, o.max_iter);
     HUB_HIP(hipGetLastError());
     const int C = mixed ? o.reliable_every : 50;
     // Every chunk either runs at least one iteration or ends the solve, so
@@ -302,8 +312,8 @@ hub_status serve_slot_init(const Geom& g, CGScalars* sc, const double* phi, floa
                            double* x, float* xlo, double tol2, double delta2, int max_iter,
                            double* partials, hipStream_t st) {
     k_zero_scalars<<<1, 64, 0, st>>>(sc);
-    k_init<float><<<elem_tiles(g.V), 256, 0, st>>>(sc, phi, r, p0, x, xlo, g.V, tol2, delta2,
-                                                   max_iter, partials);
+    k_init<float><<<elem_tiles(g.V), 256, 0, st>>>(phi, r, p0, x, xlo, g.V, partials);
+    k_init_finish<<<1, 256, 0, st>>>(sc, partials, elem_tiles(g.V), tol2, delta2, max_iter);
     HUB_HIP(hipGetLastError());
     return HUB_OK;
 }
@@ -313,7 +323,7 @@ hub_status serve_slot_final(const Geom& g, const SweepPlan& P, CGScalars* sc, co
                             const double* A64, double* partials, hipStream_t st) {
     k_fold<float><<<elem_tiles(g.V), 256, 0, st>>>(sc, kModeFinal, x, xlo, p0, p1, g.V);
     OpResidual<float> op{sc, x, phi, r, p0, p1, Link64{A64}, kModeFinal};
-    return launch_q(g, P, op, nullptr, partials, &sc->ticket, st);
+    return launch_q(g, P, op, nullptr, partials, st);
 }
 
 }  // namespace hub

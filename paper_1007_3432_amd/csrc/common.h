@@ -22,8 +22,8 @@ struct Geom {
 };
 
 // Device-resident solver state of one CG solve.  Every field is written by
-// exactly one thread: thread 0 of the block that finishes a grid reduction
-// last, or an initialisation kernel.
+// exactly one thread: thread 0 of a one-block finalize kernel, or an
+// initialisation kernel.
 struct CGScalars {
     double rho;        // current iterated r.r (FP64 accumulation)
     double rho_prev;   // r.r of the previous iteration
@@ -40,8 +40,7 @@ struct CGScalars {
     int32_t max_iter;
     int32_t done;      // see kDone* below
     int32_t reliable_updates;
-    uint32_t ticket;   // grid-reduction arrival counter (reset by the last)
-    int32_t pad[3];
+    int32_t pad[4];
 };
 
 enum : int32_t {
@@ -123,40 +122,12 @@ __device__ inline void reduce_deposits(const double* partials, int n, double (&t
 // Largest number of sums any reduction deposits per tile.
 constexpr int kMaxNP = 2;
 
-// Single-pass grid reduction of NP values per thread.  The block that owns
-// tile `slot` of `n` deposits its block sums; the block that arrives last
-// adds all deposits in tile order (reduce_deposits) and returns true with
-// the totals in `total` (valid in thread 0).  The arrival counter is reset
-// for the next launch.  partials holds NP * n doubles.
-template <int BLOCK, int NP>
-__device__ inline bool grid_sum_last(const double (&part)[NP], double* partials, int slot,
-                                     int n, uint32_t* ticket, double (&total)[NP]) {
-    static_assert(NP >= 1 && NP <= kMaxNP, "partials are sized for kMaxNP sums");
-    __shared__ int am_last;
-    double bs[NP];
-#pragma unroll
-    for (int k = 0; k < NP; ++k) bs[k] = block_sum<BLOCK>(part[k]);
-    if (threadIdx.x == 0) {
-#pragma unroll
-        for (int k = 0; k < NP; ++k)
-            __hip_atomic_store(&partials[NP * slot + k], bs[k], __ATOMIC_RELAXED,
-                               __HIP_MEMORY_SCOPE_AGENT);
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
-        const uint32_t prev = __hip_atomic_fetch_add(
-            ticket, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
-        am_last = (prev == (uint32_t)n - 1);
-    }
-    __syncthreads();
-    if (!am_last) return false;
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-    reduce_deposits<BLOCK, NP>(partials, n, total);
-    if (threadIdx.x == 0)
-        __hip_atomic_store(ticket, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    return true;
-}
-
-// Block sums of one tile into deposit slot `slot` (no arrival counting): the
-// persistent serving kernel reduces them after a grid barrier.
+// Block sums of one tile into deposit slot `slot`.  Grid reductions are two
+// kernels: every tile deposits its sums, then a one-block kernel adds the
+// deposits in tile order (reduce_deposits) and updates the solver scalars.
+// The kernel boundary in between is the device-wide synchronisation; on
+// MI355X it costs about a launch, far less than per-block release fences
+// and same-address atomics inside one kernel.
 template <int BLOCK, int NP>
 __device__ inline void deposit(const double (&part)[NP], double* partials, int slot) {
     double bs[NP];

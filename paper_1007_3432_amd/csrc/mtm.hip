@@ -22,7 +22,7 @@ static hub_status mtm_t(const Geom& g, Lnk lk, const void* x, void* z, void* scr
         HUB_HIP(hipMallocAsync((void**)&y, (size_t)g.V * sizeof(Acc), st));
         own = true;
     }
-    hub_status s = launch_q(g, P, op, y, nullptr, nullptr, st);
+    hub_status s = launch_q(g, P, op, y, nullptr, st);
     if (own) {
         hipError_t e = hipFreeAsync(y, st);
         if (s == HUB_OK && e != hipSuccess)

@@ -39,9 +39,9 @@ Link16 make_link16(const Geom& g, const void* links);
 // fused plans; see plan_sweep).
 static bool serve_supported(const SweepPlan& P) {
     if (P.kind == kSweepD1)
-        return P.variant == kD1_256x8 || P.variant == kD1_128x8 || P.variant == kD1_64x8;
+        return P.variant == kD1_256x4 || P.variant == kD1_128x4 || P.variant == kD1_64x4;
     if (P.kind == kSweepD3)
-        return P.variant == kD3_8x8x8 || P.variant == kD3_16x4x4 || P.variant == kD3_32x4x4;
+        return P.variant == kD3_8x8x8 || P.variant == kD3_16x4x4 || P.variant == kD3_32x8x4;
     return false;
 }
 
@@ -69,10 +69,11 @@ struct EpochCtl {
 
 // LDS of the largest tile the serving kernel runs (FP64 residual sweeps).
 constexpr int kServeLdsBytes = [] {
-    int m = d1_lds_elems<256, 8>();
+    int m = d1_lds_elems<256, 4>();
     m = std::max(m, d3_lds_elems<8, 8, 8>());
     m = std::max(m, d3_lds_elems<16, 4, 4>());
-    m = std::max(m, d3_lds_elems<32, 4, 4>());
+    m = std::max(m, d1_lds_elems<256, 4>());
+    m = std::max(m, d3_lds_elems<32, 8, 4>());
     return m * 8;
 }();
 
@@ -199,30 +200,30 @@ template <class Lnk>
 __device__ Sums2 serve_sweep_A(const SlotDesc* S, int tile) {
     if (S->kind == kSweepD1) {
         switch (S->variant) {
-            case kD1_256x8: return serve_tile_A<Lnk, kSweepD1, 256, 8, 0>(S, tile);
-            case kD1_128x8: return serve_tile_A<Lnk, kSweepD1, 128, 8, 0>(S, tile);
-            default: return serve_tile_A<Lnk, kSweepD1, 64, 8, 0>(S, tile);
+            case kD1_256x4: return serve_tile_A<Lnk, kSweepD1, 256, 4, 0>(S, tile);
+            case kD1_128x4: return serve_tile_A<Lnk, kSweepD1, 128, 4, 0>(S, tile);
+            default: return serve_tile_A<Lnk, kSweepD1, 64, 4, 0>(S, tile);
         }
     }
     switch (S->variant) {
         case kD3_8x8x8: return serve_tile_A<Lnk, kSweepD3, 8, 8, 8>(S, tile);
         case kD3_16x4x4: return serve_tile_A<Lnk, kSweepD3, 16, 4, 4>(S, tile);
-        default: return serve_tile_A<Lnk, kSweepD3, 32, 4, 4>(S, tile);
+        default: return serve_tile_A<Lnk, kSweepD3, 32, 8, 4>(S, tile);
     }
 }
 
 __device__ Sums2 serve_sweep_R(const SlotDesc* S, int tile) {
     if (S->kind == kSweepD1) {
         switch (S->variant) {
-            case kD1_256x8: return serve_tile_R<kSweepD1, 256, 8, 0>(S, tile);
-            case kD1_128x8: return serve_tile_R<kSweepD1, 128, 8, 0>(S, tile);
-            default: return serve_tile_R<kSweepD1, 64, 8, 0>(S, tile);
+            case kD1_256x4: return serve_tile_R<kSweepD1, 256, 4, 0>(S, tile);
+            case kD1_128x4: return serve_tile_R<kSweepD1, 128, 4, 0>(S, tile);
+            default: return serve_tile_R<kSweepD1, 64, 4, 0>(S, tile);
         }
     }
     switch (S->variant) {
         case kD3_8x8x8: return serve_tile_R<kSweepD3, 8, 8, 8>(S, tile);
         case kD3_16x4x4: return serve_tile_R<kSweepD3, 16, 4, 4>(S, tile);
-        default: return serve_tile_R<kSweepD3, 32, 4, 4>(S, tile);
+        default: return serve_tile_R<kSweepD3, 32, 8, 4>(S, tile);
     }
 }
 
@@ -306,6 +307,71 @@ __global__ __launch_bounds__(256) void k_serve_epoch(const SlotDesc* __restrict_
         if (threadIdx.x == 0) slot_residual(S).finish(tot);
         __syncthreads();
     }
+}
+
+// ---------------------------------------------------------------------------
+// Batched engine: the same phases as k_serve_epoch, one launch per phase for
+// all in-flight solves, with one-block-per-solve finalize launches in place
+// of grid barriers (kernel boundaries are the cheaper device-wide sync).
+
+template <class Lnk>
+__global__ __launch_bounds__(256) void k_serve_A(const SlotDesc* __restrict__ slots, int n) {
+    const int w = xcd_remap(blockIdx.x, gridDim.x);
+    const SlotDesc& S = slots[find_slot(slots, n, w, true)];
+    if (S.sc->done != kRunning) return;
+    const int tile = w - S.off_sweep;
+    store_deposit<1>(serve_sweep_A<Lnk>(&S, tile), S.partials, tile);
+}
+
+template <class Lnk>
+__global__ __launch_bounds__(256) void k_serve_finA(const SlotDesc* __restrict__ slots) {
+    const SlotDesc& S = slots[blockIdx.x];
+    if (S.sc->done != kRunning) return;
+    double tot[1];
+    reduce_deposits<256, 1>(S.partials, S.sweep_tiles, tot);
+    if (threadIdx.x == 0) slot_phaseA<Lnk>(S).finish(tot);
+}
+
+__global__ __launch_bounds__(256) void k_serve_B(const SlotDesc* __restrict__ slots, int n) {
+    const int w = xcd_remap(blockIdx.x, gridDim.x);
+    const SlotDesc& S = slots[find_slot(slots, n, w, false)];
+    if (S.sc->done != kRunning) return;
+    double part[1] = {0.0};
+    const int tile = w - S.off_elem;
+    tile_phaseB<float>(S.r, S.q, (float)S.sc->alpha, S.g.V, tile, part);
+    deposit<256, 1>(part, S.partials, tile);
+}
+
+__global__ __launch_bounds__(256) void k_serve_finB(const SlotDesc* __restrict__ slots) {
+    const SlotDesc& S = slots[blockIdx.x];
+    if (S.sc->done != kRunning) return;
+    double tot[1];
+    reduce_deposits<256, 1>(S.partials, S.elem_tiles, tot);
+    if (threadIdx.x == 0) finish_phaseB(S.sc, tot[0]);
+}
+
+__global__ __launch_bounds__(256) void k_serve_fold(const SlotDesc* __restrict__ slots, int n) {
+    const int w = xcd_remap(blockIdx.x, gridDim.x);
+    const SlotDesc& S = slots[find_slot(slots, n, w, false)];
+    if (!mode_runs(kModeReliable, S.sc->done)) return;
+    tile_fold<float>(S.x, S.xlo, (S.sc->iter & 1) ? S.p1 : S.p0, S.sc->alpha, S.g.V,
+                     w - S.off_elem);
+}
+
+__global__ __launch_bounds__(256) void k_serve_R(const SlotDesc* __restrict__ slots, int n) {
+    const int w = xcd_remap(blockIdx.x, gridDim.x);
+    const SlotDesc& S = slots[find_slot(slots, n, w, true)];
+    if (!mode_runs(kModeReliable, S.sc->done)) return;
+    const int tile = w - S.off_sweep;
+    store_deposit<2>(serve_sweep_R(&S, tile), S.partials, tile);
+}
+
+__global__ __launch_bounds__(256) void k_serve_finR(const SlotDesc* __restrict__ slots) {
+    const SlotDesc& S = slots[blockIdx.x];
+    if (!mode_runs(kModeReliable, S.sc->done)) return;
+    double tot[2];
+    reduce_deposits<256, 2>(S.partials, S.sweep_tiles, tot);
+    if (threadIdx.x == 0) slot_residual(S).finish(tot);
 }
 
 __global__ void k_zero_ctl(EpochCtl* c) {
@@ -633,25 +699,45 @@ hub_status run_epoch(hub_server* S) {
     if (n == 0) return HUB_OK;
     HUB_HIP(hipMemcpyAsync(S->desc_d, S->desc_h, sizeof(SlotDesc) * n, hipMemcpyHostToDevice,
                            S->stream));
-    k_zero_ctl<<<1, 64, 0, S->stream>>>(S->ctl_d);
     int iters = S->opts.cg.reliable_every;
     const SlotDesc* descp = S->desc_d;
-    EpochCtl* ctl = S->ctl_d;
-    // ~1 s of polling per barrier before giving up (a healthy barrier takes
-    // microseconds).
-    long spin_limit = 1L << 22;
-    void* args[] = {(void*)&descp, (void*)&n, (void*)&iters, (void*)&tot_sweep,
-                    (void*)&tot_elem, (void*)&ctl, (void*)&spin_limit};
-    const void* fn = S->opts.cg.link == HUB_F16 ? (const void*)k_serve_epoch<Link16>
-                                                : (const void*)k_serve_epoch<Link32>;
-    HUB_HIP(hipLaunchCooperativeKernel(fn, dim3(S->coop_grid), dim3(256), args,
-                                       kServeLdsBytes, S->stream));
+    const bool f16 = S->opts.cg.link == HUB_F16;
+    if (S->opts.engine == 1) {
+        k_zero_ctl<<<1, 64, 0, S->stream>>>(S->ctl_d);
+        EpochCtl* ctl = S->ctl_d;
+        // ~1 s of polling per barrier before giving up (a healthy barrier
+        // takes tens of microseconds).
+        long spin_limit = 1L << 22;
+        void* args[] = {(void*)&descp, (void*)&n, (void*)&iters, (void*)&tot_sweep,
+                        (void*)&tot_elem, (void*)&ctl, (void*)&spin_limit};
+        const void* fn = f16 ? (const void*)k_serve_epoch<Link16>
+                             : (const void*)k_serve_epoch<Link32>;
+        HUB_HIP(hipLaunchCooperativeKernel(fn, dim3(S->coop_grid), dim3(256), args,
+                                           kServeLdsBytes, S->stream));
+    } else {
+        const hipStream_t st = S->stream;
+        for (int it = 0; it < iters; ++it) {
+            if (f16) {
+                k_serve_A<Link16><<<tot_sweep, 256, kServeLdsBytes, st>>>(descp, n);
+                k_serve_finA<Link16><<<n, 256, 0, st>>>(descp);
+            } else {
+                k_serve_A<Link32><<<tot_sweep, 256, kServeLdsBytes, st>>>(descp, n);
+                k_serve_finA<Link32><<<n, 256, 0, st>>>(descp);
+            }
+            k_serve_B<<<tot_elem, 256, 0, st>>>(descp, n);
+            k_serve_finB<<<n, 256, 0, st>>>(descp);
+        }
+        k_serve_fold<<<tot_elem, 256, 0, st>>>(descp, n);
+        k_serve_R<<<tot_sweep, 256, kServeLdsBytes, st>>>(descp, n);
+        k_serve_finR<<<n, 256, 0, st>>>(descp);
+        HUB_HIP(hipGetLastError());
+    }
     HUB_HIP(hipMemcpyAsync(S->sc_h, S->sc_d, sizeof(CGScalars) * S->slots.size(),
                            hipMemcpyDeviceToHost, S->stream));
     HUB_HIP(hipMemcpyAsync(S->ctl_h, S->ctl_d, sizeof(EpochCtl), hipMemcpyDeviceToHost,
                            S->stream));
     HUB_HIP(hipStreamSynchronize(S->stream));
-    if (S->ctl_h->abort)
+    if (S->opts.engine == 1 && S->ctl_h->abort)
         return set_error(HUB_E_DEVICE, "serving kernel: a grid barrier timed out");
     for (int k : ks)
         if (S->sc_h[k].done >= kDoneConverged) SRV_TRY(finish_slot(S, k));
@@ -696,7 +782,9 @@ hub_status serve_validate_opts(const hub_serve_opts* o) {
     if (!o) return set_error(HUB_E_INVALID, "serve opts is NULL");
     if (o->max_inflight < 1 || o->max_inflight > 4096)
         return set_error(HUB_E_INVALID, "max_inflight = %d, expected 1..4096", o->max_inflight);
-    if (o->reserved != 0) return set_error(HUB_E_INVALID, "serve opts reserved must be 0");
+    if (o->engine != 0 && o->engine != 1)
+        return set_error(HUB_E_INVALID, "engine = %d, expected 0 (batched) or 1 (persistent)",
+                         o->engine);
     if (o->cg.bulk != HUB_F32)
         return set_error(HUB_E_INVALID, "serving runs the mixed-precision solver: cg.bulk must be F32");
     if (o->cg.link != HUB_F32 && o->cg.link != HUB_F16)
@@ -731,16 +819,19 @@ hub_status server_create(const hub_serve_opts* o, hub_server** out) {
             return fail(set_error(HUB_E_DEVICE, "%s failed: %s", #call, hipGetErrorString(e_))); \
     } while (0)
     SRV_HIP(hipGetDevice(&S->device));
-    int coop = 0, ncu = 0;
-    SRV_HIP(hipDeviceGetAttribute(&coop, hipDeviceAttributeCooperativeLaunch, S->device));
-    if (!coop) return fail(set_error(HUB_E_DEVICE, "device does not support cooperative launch"));
-    SRV_HIP(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, S->device));
-    int per_cu = 0;
-    const void* fn = o->cg.link == HUB_F16 ? (const void*)k_serve_epoch<Link16>
-                                           : (const void*)k_serve_epoch<Link32>;
-    SRV_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, 256, kServeLdsBytes));
-    if (per_cu < 1) return fail(set_error(HUB_E_DEVICE, "serving kernel does not fit a CU"));
-    S->coop_grid = per_cu * ncu;
+    if (o->engine == 1) {
+        int coop = 0, ncu = 0;
+        SRV_HIP(hipDeviceGetAttribute(&coop, hipDeviceAttributeCooperativeLaunch, S->device));
+        if (!coop)
+            return fail(set_error(HUB_E_DEVICE, "device does not support cooperative launch"));
+        SRV_HIP(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, S->device));
+        int per_cu = 0;
+        const void* fn = o->cg.link == HUB_F16 ? (const void*)k_serve_epoch<Link16>
+                                               : (const void*)k_serve_epoch<Link32>;
+        SRV_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, 256, kServeLdsBytes));
+        if (per_cu < 1) return fail(set_error(HUB_E_DEVICE, "serving kernel does not fit a CU"));
+        S->coop_grid = per_cu * ncu;
+    }
     SRV_HIP(hipStreamCreateWithFlags(&S->stream, hipStreamNonBlocking));
     const int m = o->max_inflight;
     S->slots.resize(m);

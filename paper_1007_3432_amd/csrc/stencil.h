@@ -195,6 +195,16 @@ struct OpResidual {
     }
 };
 
+// One-block finalize of an op's reduction: the deposits of n tiles in tile
+// order, then op.finish (solver scalar update).
+template <class Op>
+__global__ __launch_bounds__(256) void k_finish_op(Op op, const double* partials, int n) {
+    if (op.skip()) return;
+    double total[Op::kNP];
+    reduce_deposits<256, Op::kNP>(partials, n, total);
+    if (threadIdx.x == 0) op.finish(total);
+}
+
 // ---------------------------------------------------------------------------
 // Fused Q = M^T M sweep for d = 1.
 //
@@ -307,7 +317,7 @@ __device__ __forceinline__ void tile_mtm_d1(const Geom& g, const Op& op, int til
 
 template <class Op, int TX, int TT>
 __global__ __launch_bounds__(TX) void k_mtm_d1(Geom g, Op op, int tiles_x,
-                                               double* partials, uint32_t* ticket) {
+                                               double* partials) {
     using Acc = typename Op::acc_t;
     __shared__ Acc lds[d1_lds_elems<TX, TT>()];
     if (op.skip()) return;
@@ -315,12 +325,7 @@ __global__ __launch_bounds__(TX) void k_mtm_d1(Geom g, Op op, int tiles_x,
     const int b = xcd_remap(blockIdx.x, gridDim.x);
     double part[Op::kNP] = {};
     tile_mtm_d1<Op, TX, TT>(g, op, tiles_x, b, lds, part);
-    if constexpr (Op::kReduce) {
-        double total[Op::kNP];
-        if (grid_sum_last<TX, Op::kNP>(part, partials, b, gridDim.x, ticket, total) &&
-            threadIdx.x == 0)
-            op.finish(total);
-    }
+    if constexpr (Op::kReduce) deposit<TX, Op::kNP>(part, partials, b);
 }
 
 // ---------------------------------------------------------------------------
@@ -513,7 +518,7 @@ __device__ __forceinline__ void tile_mtm_d3(const Geom& g, const Op& op, int til
 
 template <class Op, int NX, int TY, int TZ>
 __global__ __launch_bounds__(256) void k_mtm_d3(Geom g, Op op, int tiles_y, int tiles_z,
-                                                int tc, double* partials, uint32_t* ticket) {
+                                                int tc, double* partials) {
     using Acc = typename Op::acc_t;
     __shared__ Acc lds[d3_lds_elems<NX, TY, TZ>()];
     if (op.skip()) return;
@@ -521,12 +526,7 @@ __global__ __launch_bounds__(256) void k_mtm_d3(Geom g, Op op, int tiles_y, int 
     const int b = xcd_remap(blockIdx.x, gridDim.x);
     double part[Op::kNP] = {};
     tile_mtm_d3<Op, NX, TY, TZ>(g, op, tiles_y, tiles_z, tc, b, lds, part);
-    if constexpr (Op::kReduce) {
-        double total[Op::kNP];
-        if (grid_sum_last<256, Op::kNP>(part, partials, b, gridDim.x, ticket, total) &&
-            threadIdx.x == 0)
-            op.finish(total);
-    }
+    if constexpr (Op::kReduce) deposit<256, Op::kNP>(part, partials, b);
 }
 
 // ---------------------------------------------------------------------------
@@ -561,7 +561,7 @@ __global__ __launch_bounds__(256) void k_gen_pass1(Geom g, Op op, typename Op::a
 template <class Op>
 __global__ __launch_bounds__(256) void k_gen_pass2(Geom g, Op op,
                                                    const typename Op::acc_t* y,
-                                                   double* partials, uint32_t* ticket) {
+                                                   double* partials) {
     using Acc = typename Op::acc_t;
     if (op.skip()) return;
     op.begin();
@@ -585,12 +585,7 @@ __global__ __launch_bounds__(256) void k_gen_pass2(Geom g, Op op,
         const Acc v = op.in_center(i, c);
         op.out(i, zv, v, c, part);
     }
-    if constexpr (Op::kReduce) {
-        double total[Op::kNP];
-        if (grid_sum_last<256, Op::kNP>(part, partials, blockIdx.x, gridDim.x, ticket, total) &&
-            threadIdx.x == 0)
-            op.finish(total);
-    }
+    if constexpr (Op::kReduce) deposit<256, Op::kNP>(part, partials, blockIdx.x);
 }
 
 // ---------------------------------------------------------------------------

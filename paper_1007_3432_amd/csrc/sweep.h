@@ -13,10 +13,11 @@ namespace hub {
 
 // Tile shapes of the fused d = 1 kernel: TX sites in x x TT slices.
 enum D1Tile { kD1_256x8 = 0, kD1_128x8, kD1_64x8, kD1_256x4, kD1_256x16, kD1_128x16,
-              kD1_Count };
+              kD1_256x2, kD1_256x1, kD1_128x4, kD1_64x4, kD1_Count };
 struct D1Shape { int tx, tt; };
 static constexpr D1Shape kD1Shapes[kD1_Count] = {
-    {256, 8}, {128, 8}, {64, 8}, {256, 4}, {256, 16}, {128, 16}};
+    {256, 8}, {128, 8}, {64, 8}, {256, 4}, {256, 16}, {128, 16},
+    {256, 2}, {256, 1}, {128, 4}, {64, 4}};
 
 // Tile shapes of the fused d = 3 kernel: whole rows of NX x TY x TZ.
 enum D3Tile { kD3_8x8x8 = 0, kD3_16x4x4, kD3_16x8x8, kD3_32x4x4, kD3_32x8x4, kD3_64x4x4,
@@ -88,7 +89,7 @@ inline SweepPlan plan_sweep(const Geom& g) {
     p.variant = -1;
     if (!force_generic() && g.d == 1) {
         int v = d1_tile_override();
-        if (v < 0) v = g.nx >= 256 ? kD1_256x8 : (g.nx >= 128 ? kD1_128x8 : kD1_64x8);
+        if (v < 0) v = g.nx >= 256 ? kD1_256x4 : (g.nx >= 128 ? kD1_128x4 : kD1_64x4);
         p.kind = kSweepD1;
         p.variant = v;
         p.tiles_x = ceil_div(g.nx, kD1Shapes[v].tx);
@@ -100,7 +101,7 @@ inline SweepPlan plan_sweep(const Geom& g) {
             switch (g.nx) {
                 case 8: v = kD3_8x8x8; break;
                 case 16: v = kD3_16x4x4; break;
-                case 32: v = kD3_32x4x4; break;
+                case 32: v = kD3_32x8x4; break;
                 case 64: v = kD3_64x4x4; break;
                 default: v = -1;
             }
@@ -112,9 +113,10 @@ inline SweepPlan plan_sweep(const Geom& g) {
             p.tiles_y = g.nx / sh.ty;
             p.tiles_z = g.nx / sh.tz;
             const int tiles = p.tiles_y * p.tiles_z;
-            // Aim at ~2048 blocks; longer marches amortise the prologue slice.
-            int tc = ceil_div(g.nt * tiles, 2048);
-            tc = tc < 2 ? 2 : (tc > 32 ? 32 : tc);
+            // Aim at ~1024 blocks (four per CU); longer marches amortise the
+            // prologue slice, shorter ones leave more blocks to hide latency.
+            int tc = ceil_div(g.nt * tiles, 1024);
+            tc = tc < 2 ? 2 : (tc > 16 ? 16 : tc);
             tc = env_int("HUB_D3_TC", tc);
             if (tc < 1) tc = 1;
             p.tc = tc;
@@ -138,14 +140,12 @@ inline int max_partials(const Geom& g) {
 // elements, used by the generic path only.
 template <class Op>
 hub_status launch_q(const Geom& g, const SweepPlan& P, const Op& op,
-                    typename Op::acc_t* y, double* partials, uint32_t* ticket,
-                    hipStream_t st) {
+                    typename Op::acc_t* y, double* partials, hipStream_t st) {
     if (P.kind == kSweepD1) {
         switch (P.variant) {
-#define HUB_D1_CASE(K, TX, TT)                                                   \
-    case K:                                                                      \
-        k_mtm_d1<Op, TX, TT><<<P.grid, TX, 0, st>>>(g, op, P.tiles_x, partials,  \
-                                                     ticket);                    \
+#define HUB_D1_CASE(K, TX, TT)                                                             \
+    case K:                                                                                \
+        k_mtm_d1<Op, TX, TT><<<P.grid, TX, 0, st>>>(g, op, P.tiles_x, partials);           \
         break;
             HUB_D1_CASE(kD1_256x8, 256, 8)
             HUB_D1_CASE(kD1_128x8, 128, 8)
@@ -153,6 +153,10 @@ hub_status launch_q(const Geom& g, const SweepPlan& P, const Op& op,
             HUB_D1_CASE(kD1_256x4, 256, 4)
             HUB_D1_CASE(kD1_256x16, 256, 16)
             HUB_D1_CASE(kD1_128x16, 128, 16)
+            HUB_D1_CASE(kD1_256x2, 256, 2)
+            HUB_D1_CASE(kD1_256x1, 256, 1)
+            HUB_D1_CASE(kD1_128x4, 128, 4)
+            HUB_D1_CASE(kD1_64x4, 64, 4)
 #undef HUB_D1_CASE
             default:
                 return set_error(HUB_E_INVALID, "internal: bad d=1 tile variant");
@@ -161,10 +165,10 @@ hub_status launch_q(const Geom& g, const SweepPlan& P, const Op& op,
         if (g.nx != kD3Shapes[P.variant].nx)
             return set_error(HUB_E_INVALID, "internal: d=3 tile does not fit nx");
         switch (P.variant) {
-#define HUB_D3_CASE(K, NX, TY, TZ)                                                  \
-    case K:                                                                         \
-        k_mtm_d3<Op, NX, TY, TZ><<<P.grid, 256, 0, st>>>(g, op, P.tiles_y, P.tiles_z, \
-                                                          P.tc, partials, ticket);   \
+#define HUB_D3_CASE(K, NX, TY, TZ)                                                      \
+    case K:                                                                             \
+        k_mtm_d3<Op, NX, TY, TZ><<<P.grid, 256, 0, st>>>(g, op, P.tiles_y, P.tiles_z,    \
+                                                          P.tc, partials);               \
         break;
             HUB_D3_CASE(kD3_8x8x8, 8, 8, 8)
             HUB_D3_CASE(kD3_16x4x4, 16, 4, 4)
@@ -180,7 +184,11 @@ hub_status launch_q(const Geom& g, const SweepPlan& P, const Op& op,
         if (!y) return set_error(HUB_E_INVALID, "internal: generic sweep needs scratch");
         const int grid = ceil_div(g.V, 256);
         k_gen_pass1<Op><<<grid, 256, 0, st>>>(g, op, y);
-        k_gen_pass2<Op><<<grid, 256, 0, st>>>(g, op, y, partials, ticket);
+        k_gen_pass2<Op><<<grid, 256, 0, st>>>(g, op, y, partials);
+    }
+    if constexpr (Op::kReduce) {
+        if (!partials) return set_error(HUB_E_INVALID, "internal: reduction needs deposits");
+        k_finish_op<Op><<<1, 256, 0, st>>>(op, partials, P.grid);
     }
     HUB_HIP(hipGetLastError());
     return HUB_OK;

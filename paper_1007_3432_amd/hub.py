@@ -53,7 +53,7 @@ class CGStats(ctypes.Structure):
 
 class ServeOpts(ctypes.Structure):
     _fields_ = [("hbm_budget_bytes", ctypes.c_size_t), ("max_inflight", ctypes.c_int32),
-                ("reserved", ctypes.c_int32), ("cg", CGOpts)]
+                ("engine", ctypes.c_int32), ("cg", CGOpts)]
 
 
 class HubError(RuntimeError):
@@ -184,9 +184,11 @@ def hub_cg_solve(lat: Lattice, sigma, phi, x, opts: CGOpts, stream=None,
 class Server:
     """hub_serve_*: continuous batching of CG solves for many HMC chains."""
 
-    def __init__(self, hbm_budget_bytes: int, max_inflight: int, cg: CGOpts):
+    ENGINE_BATCHED, ENGINE_PERSISTENT = 0, 1
+
+    def __init__(self, hbm_budget_bytes: int, max_inflight: int, cg: CGOpts, engine: int = 0):
         self._lib = load()
-        self._opts = ServeOpts(int(hbm_budget_bytes), int(max_inflight), 0, cg)
+        self._opts = ServeOpts(int(hbm_budget_bytes), int(max_inflight), int(engine), cg)
         h = ctypes.c_void_p()
         _check(self._lib.hub_serve_create(ctypes.byref(self._opts), ctypes.byref(h)),
                "hub_serve_create")

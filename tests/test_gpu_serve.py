@@ -66,16 +66,17 @@ def _true_resid(olat, A, phi, x):
     return float(np.linalg.norm(phi - oracle.apply_MtM(olat, A, x)) / np.linalg.norm(phi))
 
 
+@pytest.mark.parametrize("engine", [0, 1], ids=["batched", "persistent"])
 @pytest.mark.parametrize("link", [hub.F32, hub.F16], ids=["f32", "f16"])
-def test_alone_equals_mix(link):
+def test_alone_equals_mix(link, engine):
     chains = list(range(10))
     probs = {c: _chain_problem(c) for c in chains}
     shapes = {inputs.chain_shape(c) for c in chains}
     assert len(shapes) >= 3, shapes
     opts = _opts(link)
-    hubtest.log_case(f"serve alone-vs-mix link={link}")
+    hubtest.log_case(f"serve alone-vs-mix link={link} engine={engine}")
     alone = {c: _alone(p[0], p[2], p[4], opts) for c, p in probs.items()}
-    srv = hub.Server(hbm_budget_bytes=64 << 30, max_inflight=64, cg=opts)
+    srv = hub.Server(hbm_budget_bytes=64 << 30, max_inflight=64, cg=opts, engine=engine)
     try:
         tickets, sizes, owner = [], {}, {}
         for c, (lat, olat, sigma, A, phi) in probs.items():
