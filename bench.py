@@ -3,13 +3,14 @@
 One step is the d=1 2048 x 512 workload (1 048 576 sites, t=1, dtau=0.05,
 U=-2, sigma uniform, phi = M^T eta): links from sigma, phi = M^T eta, 1000
 bare hub_apply_MtM calls in FP64 cycling over 24 buffer sets (576 MiB, more
-than twice the 256 MiB Infinity Cache, so the sweeps stream from HBM), and
-one FP64 CG solve of M^T M x = phi to a true relative residual of 1e-10.
+than twice the 256 MiB Infinity Cache, so the sweeps stream from HBM),
+captured once into a HIP graph and replayed, and one FP64 CG solve of
+M^T M x = phi to a true relative residual of 1e-10.
 
 Printed: one JSON line.  `value` is the effective HBM throughput of the bare
 sweeps (24 algorithmic bytes per site: read x and A, write z) over the timed
-steps.  `roofline` prices the sweep kernel's average duration, timed with
-HIP events around each launch, against the 8 TB/s HBM peak.  `detail` holds
+steps.  `roofline` prices the sweep kernel's average duration (HIP events
+around the graph replay, divided by the calls) against the 8 TB/s HBM peak.  `detail` holds
 the CG solve rates (FP64 vs mixed precision on the d=3 workloads) and, with
 --serve, the served solves/s and latency percentiles.  `cpu_baseline` times
 the CPU oracle on a bounded sample of the same sweep on the host cores.
@@ -45,6 +46,9 @@ def _args():
     ap.add_argument("--engine", type=int, default=0, help="serving engine: 0 batched, 1 persistent")
     ap.add_argument("--serve-seconds", type=float, default=15.0)
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--direct", action="store_true",
+                    help="launch the bare sweeps one by one instead of replaying a graph "
+                         "(for counter collection)")
     ap.add_argument("--copy-calib", action="store_true",
                     help="run one 256 MiB device copy (counter calibration)")
     return ap.parse_args()
@@ -237,42 +241,66 @@ def main():
         dst.copy_(src)
         torch.cuda.synchronize()
 
-    def step(timed: bool):
+    # The 1000 bare sweeps are captured once into a HIP graph and replayed
+    # each step (the host would otherwise spend longer issuing 1000 launches
+    # through ctypes than the GPU spends running them).
+    for k in range(nsets):
+        hub.hub_links_from_sigma(lat, sig_d, links[k], hub.F64)
+    for k in range(nsets):
+        hub.hub_apply_MtM(lat, links[k], hub.F64, hub.F64, xs[k], zs[k])
+    torch.cuda.synchronize()
+    def sweeps():
+        for c in range(a.calls):
+            k = c % nsets
+            hub.hub_apply_MtM(lat, links[k], hub.F64, hub.F64, xs[k], zs[k])
+
+    graph = None
+    if not a.direct:
+        graph = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(graph):
+            sweeps()
+    torch.cuda.synchronize()
+
+    def step():
         for k in range(nsets):
             hub.hub_links_from_sigma(lat, sig_d, links[k], hub.F64)
         hub.hub_apply_M(lat, links[0], hub.F64, hub.F64, eta_d, phi, 1)
-        ev = []
         s0 = torch.cuda.Event(enable_timing=True)
         s1 = torch.cuda.Event(enable_timing=True)
         s0.record()
-        for c in range(a.calls):
-            k = c % nsets
-            if timed:
-                e0 = torch.cuda.Event(enable_timing=True)
-                e1 = torch.cuda.Event(enable_timing=True)
-                e0.record()
-            hub.hub_apply_MtM(lat, links[k], hub.F64, hub.F64, xs[k], zs[k])
-            if timed:
-                e1.record()
-                ev.append((e0, e1))
+        if graph is not None:
+            graph.replay()
+        else:
+            sweeps()
         s1.record()
         st = hub.hub_cg_solve(lat, sig_d, phi, x_cg, opts)
-        return s0, s1, ev, st
+        return s0, s1, st
 
     for _ in range(a.warmup):
-        step(False)
+        step()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    recs = [step(True) for _ in range(a.steps)]
+    recs = [step() for _ in range(a.steps)]
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
 
-    sweep_ms = sum(s0.elapsed_time(s1) for s0, s1, _, _ in recs)
-    kern_ms = [e0.elapsed_time(e1) for _, _, ev, _ in recs for e0, e1 in ev]
-    avg_kern_s = statistics.mean(kern_ms) / 1e3
+    sweep_ms = sum(s0.elapsed_time(s1) for s0, s1, _ in recs)
+    avg_kern_s = sweep_ms / 1e3 / (a.calls * a.steps)
     value = SWEEP_BYTES_F64 * V * a.calls * a.steps / (sweep_ms / 1e3) / 1e9
     achieved = SWEEP_BYTES_F64 * V / avg_kern_s / 1e9
-    cg_stats = [r[3] for r in recs]
+
+    # For reference: the same sweeps launched one by one from Python.
+    torch.cuda.synchronize()
+    d0 = torch.cuda.Event(enable_timing=True)
+    d1 = torch.cuda.Event(enable_timing=True)
+    d0.record()
+    for c in range(200):
+        k = c % nsets
+        hub.hub_apply_MtM(lat, links[k], hub.F64, hub.F64, xs[k], zs[k])
+    d1.record()
+    torch.cuda.synchronize()
+    direct_us = d0.elapsed_time(d1) * 1e3 / 200
+    cg_stats = [r[2] for r in recs]
     cg_ms = [s["ms"] for s in cg_stats]
     cg_iters = cg_stats[-1]["iters"]
     line = {
@@ -291,9 +319,13 @@ def main():
                      "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None,
                      "kernel": "k_mtm_d1<OpApply<double>> (fused M^T M sweep)",
                      "avg_launch_us": avg_kern_s * 1e6,
-                     "bytes_per_launch": SWEEP_BYTES_F64 * V},
+                     "bytes_per_launch": SWEEP_BYTES_F64 * V,
+                     "timing": ("HIP events around the sweeps launched one by one, / calls"
+                                if a.direct else
+                                "HIP events around a graph replay of the sweeps, / calls")},
         "detail": {
-            "sweep_section_gbs_incl_launch_gaps": value,
+            "sweep_direct_launch_us": direct_us,
+            "sweep_direct_launch_gbs": SWEEP_BYTES_F64 * V / direct_us / 1e3,
             "cg_fp64_c1": {"iters": cg_iters, "device_ms_per_solve": statistics.mean(cg_ms),
                            "solves_per_s": 1e3 / statistics.mean(cg_ms),
                            "true_rel_resid": cg_stats[-1]["true_rel_resid"],

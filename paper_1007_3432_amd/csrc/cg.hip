@@ -12,6 +12,7 @@
 // true-residual sweep: always in the mixed solver (the reliable update),
 // only after an iterated convergence in the FP64 solver.
 #include <cmath>
+#include <cstdlib>
 
 #include "cgtiles.h"
 #include "sweep.h"
@@ -85,13 +86,15 @@ struct HostCtx {
     int device = -1;
     CGScalars* snap = nullptr;  // [2], pinned
     hipEvent_t ev[2] = {nullptr, nullptr};
-    hipEvent_t t0 = nullptr, t1 = nullptr;
+    hipEvent_t t0 = nullptr, t1 = nullptr, in_ev = nullptr;
+    hipStream_t stream = nullptr;  // the solve runs (and is captured) here
     ~HostCtx() {
         if (device < 0) return;
         (void)hipSetDevice(device);
         if (snap) (void)hipHostFree(snap);
-        for (auto e : {ev[0], ev[1], t0, t1})
+        for (auto e : {ev[0], ev[1], t0, t1, in_ev})
             if (e) (void)hipEventDestroy(e);
+        if (stream) (void)hipStreamDestroy(stream);
     }
     hub_status ensure() {
         int dev = 0;
@@ -103,6 +106,8 @@ struct HostCtx {
         HUB_HIP(hipEventCreateWithFlags(&ev[1], hipEventDisableTiming));
         HUB_HIP(hipEventCreate(&t0));
         HUB_HIP(hipEventCreate(&t1));
+        HUB_HIP(hipEventCreateWithFlags(&in_ev, hipEventDisableTiming));
+        HUB_HIP(hipStreamCreateWithFlags(&stream, hipStreamNonBlocking));
         device = dev;
         return HUB_OK;
     }
@@ -139,7 +144,9 @@ struct Solver {
         return launch_q(g, P, op, yscratch, partials, st);
     }
 
-    hub_status chunk(int iters, CGScalars* snap, hipEvent_t ev, bool mixed) {
+    // One chunk of `iters` iterations and its closing fold / true residual,
+    // then the scalars into `snap` (pinned).  Captured once into a graph.
+    hub_status chunk(int iters, CGScalars* snap, bool mixed) {
         OpPhaseA<Vec, Vec, typename std::conditional<sizeof(Vec) == 8, double, float>::type, Lnk>
             opA{};
         opA.sc = sc;
@@ -156,17 +163,59 @@ struct Solver {
         }
         HUB_TRY(fold_and_residual(mixed ? kModeReliable : kModeCheck));
         HUB_HIP(hipMemcpyAsync(snap, sc, sizeof(CGScalars), hipMemcpyDeviceToHost, st));
-        HUB_HIP(hipEventRecord(ev, st));
         return HUB_OK;
     }
 };
+
+// Chunks are captured into two HIP graphs (one per snapshot buffer) and
+// replayed: the host then pays one graph launch per chunk instead of four
+// kernel launches per iteration.  HUB_CG_GRAPH=0 launches kernels directly.
+inline bool use_graphs() {
+    static bool v = [] {
+        const char* e = std::getenv("HUB_CG_GRAPH");
+        return !(e && e[0] == '0');
+    }();
+    return v;
+}
+
+struct GraphPair {
+    hipGraphExec_t ex[2] = {nullptr, nullptr};
+    ~GraphPair() {
+        for (auto e : ex)
+            if (e) (void)hipGraphExecDestroy(e);
+    }
+};
+
+template <class Vec, class Lnk>
+hub_status capture_chunk(Solver<Vec, Lnk>& S, int iters, CGScalars* snap, bool mixed,
+                         hipGraphExec_t* out) {
+    HUB_HIP(hipStreamBeginCapture(S.st, hipStreamCaptureModeThreadLocal));
+    const hub_status body = S.chunk(iters, snap, mixed);
+    hipGraph_t gr = nullptr;
+    const hipError_t e = hipStreamEndCapture(S.st, &gr);
+    if (body != HUB_OK) {
+        if (gr) (void)hipGraphDestroy(gr);
+        return body;
+    }
+    if (e != hipSuccess)
+        return set_error(HUB_E_DEVICE, "hipStreamEndCapture: %s", hipGetErrorString(e));
+    const hipError_t e2 = hipGraphInstantiate(out, gr, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(gr);
+    if (e2 != hipSuccess)
+        return set_error(HUB_E_DEVICE, "hipGraphInstantiate: %s", hipGetErrorString(e2));
+    return HUB_OK;
+}
 
 template <class Vec, class Lnk>
 hub_status run_solver(Solver<Vec, Lnk>& S, bool mixed, hub_cg_stats* out) {
     const Geom& g = S.g;
     const hub_cg_opts& o = S.o;
-    hipStream_t st = S.st;
     HostCtx& H = g_ctx;
+    // Work the caller queued on its stream (sigma, phi) comes first.
+    HUB_HIP(hipEventRecord(H.in_ev, S.st));
+    HUB_HIP(hipStreamWaitEvent(H.stream, H.in_ev, 0));
+    S.st = H.stream;
+    hipStream_t st = S.st;
     HUB_HIP(hipEventRecord(H.t0, st));
     k_zero_scalars<<<1, 64, 0, st>>>(S.sc);
     k_init<Vec><<<elem_tiles(g.V), 256, 0, st>>>(S.phi, S.r, S.p0, S.x, S.xlo, g.V, S.partials);
@@ -174,11 +223,26 @@ hub_status run_solver(Solver<Vec, Lnk>& S, bool mixed, hub_cg_stats* out) {
                                      mixed ? kReliableDelta * kReliableDelta : 0.0, o.max_iter);
     HUB_HIP(hipGetLastError());
     const int C = mixed ? o.reliable_every : 50;
+    GraphPair G;
+    const bool graphs = use_graphs();
+    if (graphs) {
+        HUB_TRY(capture_chunk(S, C, &H.snap[0], mixed, &G.ex[0]));
+        HUB_TRY(capture_chunk(S, C, &H.snap[1], mixed, &G.ex[1]));
+    }
+    auto enqueue = [&](int slot) -> hub_status {
+        if (graphs) {
+            HUB_HIP(hipGraphLaunch(G.ex[slot], st));
+        } else {
+            HUB_TRY(S.chunk(C, &H.snap[slot], mixed));
+        }
+        HUB_HIP(hipEventRecord(H.ev[slot], st));
+        return HUB_OK;
+    };
     // Every chunk either runs at least one iteration or ends the solve, so
     // this bound is never reached by a healthy solve.
     const long long max_chunks = 2LL * (o.max_iter / C + 2) + 8;
-    HUB_TRY(S.chunk(C, &H.snap[0], H.ev[0], mixed));
-    HUB_TRY(S.chunk(C, &H.snap[1], H.ev[1], mixed));
+    HUB_TRY(enqueue(0));
+    HUB_TRY(enqueue(1));
     long long enq = 2;
     int cur = 0;
     CGScalars s{};
@@ -190,7 +254,7 @@ hub_status run_solver(Solver<Vec, Lnk>& S, bool mixed, hub_cg_stats* out) {
             (void)hipStreamSynchronize(st);
             return set_error(HUB_E_NOCONV, "hub_cg_solve: chunk limit reached");
         }
-        HUB_TRY(S.chunk(C, &H.snap[cur], H.ev[cur], mixed));
+        HUB_TRY(enqueue(cur));
         ++enq;
         cur ^= 1;
     }
@@ -294,6 +358,9 @@ hub_status cg_solve(const Geom& g, const double* sigma, const double* phi, doubl
             result = run_solver(S, true, out);
         }
     }
+    // The solve ran on the context stream: let it drain (also on an error
+    // path) before the workspace goes back to the caller's stream.
+    (void)hipStreamSynchronize(g_ctx.stream);
     hipError_t e = hipFreeAsync(ws, st);
     hipError_t e2 = hipStreamSynchronize(st);
     if (result == HUB_OK && (e != hipSuccess || e2 != hipSuccess))
