@@ -289,6 +289,29 @@ def main():
     value = SWEEP_BYTES_F64 * V * a.calls * a.steps / (sweep_ms / 1e3) / 1e9
     achieved = SWEEP_BYTES_F64 * V / avg_kern_s / 1e9
 
+    # Context: a plain streaming kernel (torch's z = x + a) over the same
+    # rotating buffers moves the same 24 B/site; its rate is the practical
+    # HBM ceiling at this transfer size.
+    def adds():
+        for c in range(a.calls):
+            k = c % nsets
+            torch.add(xs[k], links[k], out=zs[k])
+    adds()
+    torch.cuda.synchronize()
+    add_graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(add_graph):
+        adds()
+    add_graph.replay()
+    torch.cuda.synchronize()
+    c0 = torch.cuda.Event(enable_timing=True)
+    c1 = torch.cuda.Event(enable_timing=True)
+    c0.record()
+    add_graph.replay()
+    c1.record()
+    torch.cuda.synchronize()
+    add_us = c0.elapsed_time(c1) * 1e3 / a.calls
+    del add_graph
+
     # For reference: the same sweeps launched one by one from Python.
     torch.cuda.synchronize()
     d0 = torch.cuda.Event(enable_timing=True)
@@ -324,6 +347,9 @@ def main():
                                 if a.direct else
                                 "HIP events around a graph replay of the sweeps, / calls")},
         "detail": {
+            "stream_add_same_bytes_us": add_us,
+            "stream_add_same_bytes_gbs": SWEEP_BYTES_F64 * V / add_us / 1e3,
+            "sweep_vs_stream_add": add_us / avg_kern_s / 1e6,
             "sweep_direct_launch_us": direct_us,
             "sweep_direct_launch_gbs": SWEEP_BYTES_F64 * V / direct_us / 1e3,
             "cg_fp64_c1": {"iters": cg_iters, "device_ms_per_solve": statistics.mean(cg_ms),

@@ -18,6 +18,12 @@ Parity status of each function (the pins live under ``tests/``):
   apply_MtM          pinned: composition, eigenvalues |lambda|^2
   cg                 pinned: dense solve, finite termination on few
                      distinct eigenvalues, true residual
+  cheb_roots/norm    pinned: error bound of Eq. (16) on (eps, 1], near
+                     equioscillation
+  cheb_apply         pinned: dense eigen-decomposition of Q/scale with the
+                     scalar polynomial
+  cheb_scale         pinned: bound >= largest eigenvalue of Q (dense)
+  pcg                pinned: dense solve, fewer iterations than CG
 """
 from __future__ import annotations
 
@@ -106,6 +112,16 @@ def _load():
     lib.oracle_cg.argtypes = [lp, dp, dp, dp, ctypes.c_double, ctypes.c_int32,
                               ctypes.POINTER(_CGResult), dp, dp]
     lib.oracle_cg.restype = ctypes.c_int
+    lib.oracle_cheb_roots.argtypes = [ctypes.c_int32, ctypes.c_double, dp, dp]
+    lib.oracle_cheb_roots.restype = None
+    lib.oracle_cheb_norm.argtypes = [ctypes.c_int32, ctypes.c_double]
+    lib.oracle_cheb_norm.restype = ctypes.c_double
+    lib.oracle_cheb_apply.argtypes = [lp, dp, ctypes.c_double, ctypes.c_int32, ctypes.c_double,
+                                      dp, dp]
+    lib.oracle_cheb_apply.restype = ctypes.c_int
+    lib.oracle_pcg.argtypes = [lp, dp, dp, dp, ctypes.c_double, ctypes.c_int32, ctypes.c_double,
+                               ctypes.c_int32, ctypes.c_double, ctypes.POINTER(_CGResult)]
+    lib.oracle_pcg.restype = ctypes.c_int
     lib.oracle_set_threads.argtypes = [ctypes.c_int]
     lib.oracle_set_threads.restype = ctypes.c_int
     _lib = lib
@@ -195,3 +211,55 @@ def cg(lat: Lattice, A, phi, tol: float = 1e-10, max_iter: int = 200000,
     if record:
         return x, out, (al[:res.iters], be[:max(res.iters - 1, 0)])
     return x, out
+
+
+# --- Chebyshev polynomial preconditioner (Sec. 4.2, Eqs. (13)-(15)) ---
+
+def cheb_roots(n: int, eps: float) -> np.ndarray:
+    """z_{2n,k}, k = 1 .. 2n, as complex numbers."""
+    re = np.empty(2 * n)
+    im = np.empty(2 * n)
+    _load().oracle_cheb_roots(int(n), float(eps), _ptr(re), _ptr(im))
+    return re + 1j * im
+
+
+def cheb_norm(n: int, eps: float) -> float:
+    """c_{2n}."""
+    return _load().oracle_cheb_norm(int(n), float(eps))
+
+
+def cheb_scale(lat: Lattice) -> float:
+    """Bound on the largest eigenvalue of Q: |M| <= 1 + 2 d kappa + max|A|
+    (triangle inequality over the stencil's terms), max|A| <= e^{dtau mu}(1+b)."""
+    kappa = lat.dtau * lat.t_hop
+    amax = np.exp(lat.dtau * lat.mu) * (1.0 + hs_coupling(lat.dtau, lat.U))
+    return (1.0 + 2 * lat.d * kappa + amax) ** 2
+
+
+def cheb_apply(lat: Lattice, A, r, n: int, eps: float, scale: float | None = None) -> np.ndarray:
+    """z = P(Q / scale) r."""
+    A = _vec(A, lat.volume)
+    r = _vec(r, lat.volume)
+    z = np.empty(lat.volume)
+    s = cheb_scale(lat) if scale is None else float(scale)
+    rc = _load().oracle_cheb_apply(ctypes.byref(lat._c()), _ptr(A), s, int(n), float(eps),
+                                   _ptr(r), _ptr(z))
+    if rc < 0:
+        raise MemoryError("oracle_cheb_apply: allocation failed")
+    return z
+
+
+def pcg(lat: Lattice, A, phi, n: int, eps: float, tol: float = 1e-10,
+        max_iter: int = 200000, scale: float | None = None):
+    """Chebyshev-preconditioned CG; returns (x, CGResult)."""
+    A = _vec(A, lat.volume)
+    phi = _vec(phi, lat.volume)
+    x = np.empty(lat.volume)
+    res = _CGResult()
+    s = cheb_scale(lat) if scale is None else float(scale)
+    rc = _load().oracle_pcg(ctypes.byref(lat._c()), _ptr(A), _ptr(phi), _ptr(x), float(tol),
+                            int(max_iter), s, int(n), float(eps), ctypes.byref(res))
+    if rc < 0:
+        raise MemoryError("oracle_pcg: allocation failed")
+    return x, CGResult(res.iters, bool(res.converged), bool(res.breakdown),
+                       res.restarts, res.true_rel_resid, res.iter_rel_resid)

@@ -246,6 +246,142 @@ out:
     return status;
 }
 
+/* ---------------------------------------------------------------------------
+ * Chebyshev polynomial preconditioner (Sec. 4.2, Eqs. (13)-(15)).
+ *
+ * With Q normalised so that its eigenvalues lie in [0, 1] (Qn = Q / scale),
+ *   P(Qn) = c_{2n} prod_{k=1}^{2n} (Qn - z_{2n,k})
+ *   z_{2n,k} = (1+eps)/2 [1 - cos(2 pi k/(2n+1))] - i sqrt(eps) sin(2 pi k/(2n+1))
+ *   1/c_{2n} = (1+eps)/2 prod_{k=1}^{2n} ((1+eps)/2 - z_{2n,k})
+ * approximates Qn^{-1} on (eps, 1].  The oracle applies the 2n complex
+ * linear factors one after the other, k = 1 .. 2n, on a complex vector. */
+
+void oracle_cheb_roots(int32_t n, double eps, double* re, double* im) {
+    const double pi = 3.14159265358979323846;
+    for (int32_t k = 1; k <= 2 * n; ++k) {
+        double th = 2.0 * pi * (double)k / (double)(2 * n + 1);
+        re[k - 1] = 0.5 * (1.0 + eps) * (1.0 - cos(th));
+        im[k - 1] = -sqrt(eps) * sin(th);
+    }
+}
+
+/* c_{2n} (real: the roots come in conjugate pairs). */
+double oracle_cheb_norm(int32_t n, double eps) {
+    double* re = (double*)malloc(sizeof(double) * 2 * n);
+    double* im = (double*)malloc(sizeof(double) * 2 * n);
+    if (!re || !im) { free(re); free(im); return NAN; }
+    oracle_cheb_roots(n, eps, re, im);
+    double h = 0.5 * (1.0 + eps);
+    double pr = h, pi_ = 0.0;   /* running complex product, starts at (1+eps)/2 */
+    for (int32_t k = 0; k < 2 * n; ++k) {
+        double ar = h - re[k], ai = -im[k];
+        double nr = pr * ar - pi_ * ai, ni = pr * ai + pi_ * ar;
+        pr = nr;
+        pi_ = ni;
+    }
+    free(re);
+    free(im);
+    return 1.0 / pr;
+}
+
+/* z = P(Q / scale) r. */
+int oracle_cheb_apply(const oracle_lattice* L, const double* A, double scale, int32_t n,
+                      double eps, const double* r, double* z) {
+    long V = oracle_volume(L);
+    double* vr = (double*)malloc(sizeof(double) * V);
+    double* vi = (double*)malloc(sizeof(double) * V);
+    double* qr = (double*)malloc(sizeof(double) * V);
+    double* qi = (double*)malloc(sizeof(double) * V);
+    double* tmp = (double*)malloc(sizeof(double) * V);
+    double* re = (double*)malloc(sizeof(double) * 2 * n);
+    double* im = (double*)malloc(sizeof(double) * 2 * n);
+    if (!vr || !vi || !qr || !qi || !tmp || !re || !im) {
+        free(vr); free(vi); free(qr); free(qi); free(tmp); free(re); free(im);
+        return -1;
+    }
+    oracle_cheb_roots(n, eps, re, im);
+    double c = oracle_cheb_norm(n, eps);
+    for (long i = 0; i < V; ++i) { vr[i] = r[i]; vi[i] = 0.0; }
+    for (int32_t k = 0; k < 2 * n; ++k) {
+        /* v <- (Qn - z_k) v, complex v = vr + i vi, real Qn */
+        oracle_apply_MtM(L, A, vr, qr, tmp);
+        oracle_apply_MtM(L, A, vi, qi, tmp);
+        for (long i = 0; i < V; ++i) {
+            double ar = qr[i] / scale - (re[k] * vr[i] - im[k] * vi[i]);
+            double ai = qi[i] / scale - (re[k] * vi[i] + im[k] * vr[i]);
+            vr[i] = ar;
+            vi[i] = ai;
+        }
+    }
+    for (long i = 0; i < V; ++i) z[i] = c * vr[i];
+    free(vr); free(vi); free(qr); free(qi); free(tmp); free(re); free(im);
+    return 0;
+}
+
+/* Preconditioned CG on Q x = phi with z = P(Q / scale) r (Sec. 4.2), x0 = 0,
+ * stopped on the true residual as oracle_cg.  Returns as oracle_cg. */
+int oracle_pcg(const oracle_lattice* L, const double* A, const double* phi, double* x,
+               double tol, int32_t max_iter, double scale, int32_t n, double eps,
+               oracle_cg_result* res) {
+    long V = oracle_volume(L);
+    double* r = (double*)malloc(sizeof(double) * V);
+    double* z = (double*)malloc(sizeof(double) * V);
+    double* p = (double*)malloc(sizeof(double) * V);
+    double* q = (double*)malloc(sizeof(double) * V);
+    double* tmp = (double*)malloc(sizeof(double) * V);
+    if (!r || !z || !p || !q || !tmp) {
+        free(r); free(z); free(p); free(q); free(tmp);
+        return -1;
+    }
+    memset(res, 0, sizeof(*res));
+    double phinorm = sqrt(oracle_dot(V, phi, phi));
+    for (long i = 0; i < V; ++i) {
+        x[i] = 0.0;
+        r[i] = phi[i];
+    }
+    int status = 1;
+    if (phinorm == 0.0) {
+        res->converged = 1;
+        status = 0;
+        goto out;
+    }
+    if (oracle_cheb_apply(L, A, scale, n, eps, r, z) != 0) { status = -1; goto out; }
+    for (long i = 0; i < V; ++i) p[i] = z[i];
+    double rho = oracle_dot(V, r, z);
+    for (int32_t k = 1; k <= max_iter; ++k) {
+        oracle_apply_MtM(L, A, p, q, tmp);
+        double pq = oracle_dot(V, p, q);
+        res->iters = k;
+        if (!(pq > 0.0) || !isfinite(pq)) { res->breakdown = 1; break; }
+        double alpha = rho / pq;
+        for (long i = 0; i < V; ++i) x[i] += alpha * p[i];
+        for (long i = 0; i < V; ++i) r[i] -= alpha * q[i];
+        double rr = oracle_dot(V, r, r);
+        if (!isfinite(rr)) { res->breakdown = 1; break; }
+        int restart = 0;
+        if (sqrt(rr) / phinorm <= tol) {
+            oracle_apply_MtM(L, A, x, q, tmp);
+            for (long i = 0; i < V; ++i) r[i] = phi[i] - q[i];
+            rr = oracle_dot(V, r, r);
+            if (sqrt(rr) / phinorm <= tol) { res->converged = 1; status = 0; break; }
+            res->restarts += 1;
+            restart = 1;
+        }
+        if (oracle_cheb_apply(L, A, scale, n, eps, r, z) != 0) { status = -1; break; }
+        double rho_new = oracle_dot(V, r, z);
+        double beta = restart ? 0.0 : rho_new / rho;
+        for (long i = 0; i < V; ++i) p[i] = z[i] + beta * p[i];
+        rho = rho_new;
+    }
+out:
+    res->iter_rel_resid = (phinorm > 0.0) ? sqrt(oracle_dot(V, r, r)) / phinorm : 0.0;
+    oracle_apply_MtM(L, A, x, q, tmp);
+    for (long i = 0; i < V; ++i) q[i] = phi[i] - q[i];
+    res->true_rel_resid = (phinorm > 0.0) ? sqrt(oracle_dot(V, q, q)) / phinorm : 0.0;
+    free(r); free(z); free(p); free(q); free(tmp);
+    return status;
+}
+
 /* Number of OpenMP threads the stencil loops use (1 without OpenMP). */
 int oracle_set_threads(int n) {
 #ifdef _OPENMP

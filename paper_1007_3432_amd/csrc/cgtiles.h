@@ -8,11 +8,56 @@
 
 namespace hub {
 
-// Sites per element-wise tile: 256 lanes x 8 sites, lane t handling sites
-// tile*kETile + t + 256 k.
+// Sites per element-wise tile: 256 lanes x 8 consecutive sites, lane t
+// handling sites tile*kETile + 8t .. 8t+7 with 16-byte vector accesses.
 constexpr int kETile = 2048;
 
 __host__ __device__ inline int elem_tiles(int V) { return (V + kETile - 1) / kETile; }
+
+// Eight consecutive elements starting at p (16-byte aligned when full).
+template <class T>
+__device__ __forceinline__ void ld8(const T* __restrict__ p, T (&v)[8]) {
+    if constexpr (sizeof(T) == 8) {
+        const double2* q = reinterpret_cast<const double2*>(p);
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            const double2 w = q[k];
+            v[2 * k] = w.x;
+            v[2 * k + 1] = w.y;
+        }
+    } else {
+        const float4* q = reinterpret_cast<const float4*>(p);
+#pragma unroll
+        for (int k = 0; k < 2; ++k) {
+            const float4 w = q[k];
+            v[4 * k] = w.x;
+            v[4 * k + 1] = w.y;
+            v[4 * k + 2] = w.z;
+            v[4 * k + 3] = w.w;
+        }
+    }
+}
+
+template <class T>
+__device__ __forceinline__ void st8(T* __restrict__ p, const T (&v)[8]) {
+    if constexpr (sizeof(T) == 8) {
+        double2* q = reinterpret_cast<double2*>(p);
+#pragma unroll
+        for (int k = 0; k < 4; ++k) q[k] = make_double2(v[2 * k], v[2 * k + 1]);
+    } else {
+        float4* q = reinterpret_cast<float4*>(p);
+#pragma unroll
+        for (int k = 0; k < 2; ++k)
+            q[k] = make_float4(v[4 * k], v[4 * k + 1], v[4 * k + 2], v[4 * k + 3]);
+    }
+}
+
+// Lane's first site and how many of its 8 sites are inside [0, V).
+__device__ __forceinline__ int lane_base(int tile) { return tile * kETile + 8 * threadIdx.x; }
+__device__ __forceinline__ int lane_count(int base, int V) {
+    const int c = V - base;
+    return c >= 8 ? 8 : (c < 0 ? 0 : c);
+}
 
 // r = phi, p0 = 0, x = 0 (x_lo = 0); part[0] += phi.phi.
 template <class RVec>
@@ -20,20 +65,39 @@ __device__ __forceinline__ void tile_init(const double* __restrict__ phi, RVec* 
                                           RVec* __restrict__ p0, double* __restrict__ x,
                                           float* __restrict__ xlo, int V, int tile,
                                           double (&part)[1]) {
-    const int base = tile * kETile + threadIdx.x;
+    const int base = lane_base(tile), cnt = lane_count(base, V);
     double f[8];
+    if (cnt == 8) {
+        ld8(phi + base, f);
+    } else {
 #pragma unroll
-    for (int k = 0; k < 8; ++k) f[k] = phi[min(base + 256 * k, V - 1)];
+        for (int k = 0; k < 8; ++k) f[k] = k < cnt ? phi[base + k] : 0.0;
+    }
+    RVec rv[8], zr[8];
+    double zd[8];
+    float zf[8];
 #pragma unroll
     for (int k = 0; k < 8; ++k) {
-        const int i = base + 256 * k;
-        if (i < V) {
-            r[i] = (RVec)f[k];
-            p0[i] = (RVec)0;
-            x[i] = 0.0;
-            if (xlo) xlo[i] = 0.0f;
-            part[0] += f[k] * f[k];
-        }
+        rv[k] = (RVec)f[k];
+        zr[k] = (RVec)0;
+        zd[k] = 0.0;
+        zf[k] = 0.0f;
+        part[0] += f[k] * f[k];
+    }
+    if (cnt == 8) {
+        st8(r + base, rv);
+        st8(p0 + base, zr);
+        st8(x + base, zd);
+        if (xlo) st8(xlo + base, zf);
+    } else {
+#pragma unroll
+        for (int k = 0; k < 8; ++k)
+            if (k < cnt) {
+                r[base + k] = rv[k];
+                p0[base + k] = (RVec)0;
+                x[base + k] = 0.0;
+                if (xlo) xlo[base + k] = 0.0f;
+            }
     }
 }
 
@@ -59,22 +123,29 @@ __device__ __forceinline__ void finish_init(CGScalars* sc, double total, double 
 template <class Vec>
 __device__ __forceinline__ void tile_phaseB(Vec* __restrict__ r, const Vec* __restrict__ q,
                                             Vec alpha, int V, int tile, double (&part)[1]) {
-    const int base = tile * kETile + threadIdx.x;
+    const int base = lane_base(tile), cnt = lane_count(base, V);
     Vec rv[8], qv[8];
+    if (cnt == 8) {
+        ld8(r + base, rv);
+        ld8(q + base, qv);
+    } else {
 #pragma unroll
-    for (int k = 0; k < 8; ++k) {
-        const int i = min(base + 256 * k, V - 1);
-        rv[k] = r[i];
-        qv[k] = q[i];
+        for (int k = 0; k < 8; ++k) {
+            rv[k] = k < cnt ? r[base + k] : (Vec)0;
+            qv[k] = k < cnt ? q[base + k] : (Vec)0;
+        }
     }
 #pragma unroll
     for (int k = 0; k < 8; ++k) {
-        const int i = base + 256 * k;
-        if (i < V) {
-            const Vec v = rv[k] - alpha * qv[k];
-            r[i] = v;
-            part[0] += (double)v * (double)v;
-        }
+        rv[k] = rv[k] - alpha * qv[k];
+        part[0] += (double)rv[k] * (double)rv[k];
+    }
+    if (cnt == 8) {
+        st8(r + base, rv);
+    } else {
+#pragma unroll
+        for (int k = 0; k < 8; ++k)
+            if (k < cnt) r[base + k] = rv[k];
     }
 }
 
@@ -100,22 +171,42 @@ template <class PVec>
 __device__ __forceinline__ void tile_fold(double* __restrict__ x, float* __restrict__ xlo,
                                           const PVec* __restrict__ p, double alpha, int V,
                                           int tile) {
-    const int base = tile * kETile + threadIdx.x;
-    double xv[8], pv[8], lv[8];
+    const int base = lane_base(tile), cnt = lane_count(base, V);
+    double xv[8];
+    PVec pv[8];
+    float lv[8];
+    if (cnt == 8) {
+        ld8(x + base, xv);
+        ld8(p + base, pv);
+        if (xlo) ld8(xlo + base, lv);
+    } else {
 #pragma unroll
-    for (int k = 0; k < 8; ++k) {
-        const int i = min(base + 256 * k, V - 1);
-        xv[k] = x[i];
-        pv[k] = (double)p[i];
-        lv[k] = xlo ? (double)xlo[i] : 0.0;
-    }
-#pragma unroll
-    for (int k = 0; k < 8; ++k) {
-        const int i = base + 256 * k;
-        if (i < V) {
-            x[i] = xv[k] + alpha * pv[k] + lv[k];
-            if (xlo) xlo[i] = 0.0f;
+        for (int k = 0; k < 8; ++k) {
+            xv[k] = k < cnt ? x[base + k] : 0.0;
+            pv[k] = k < cnt ? p[base + k] : (PVec)0;
+            lv[k] = (xlo && k < cnt) ? xlo[base + k] : 0.0f;
         }
+    }
+    if (!xlo) {
+#pragma unroll
+        for (int k = 0; k < 8; ++k) lv[k] = 0.0f;
+    }
+    float zf[8];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+        xv[k] = xv[k] + alpha * (double)pv[k] + (double)lv[k];
+        zf[k] = 0.0f;
+    }
+    if (cnt == 8) {
+        st8(x + base, xv);
+        if (xlo) st8(xlo + base, zf);
+    } else {
+#pragma unroll
+        for (int k = 0; k < 8; ++k)
+            if (k < cnt) {
+                x[base + k] = xv[k];
+                if (xlo) xlo[base + k] = 0.0f;
+            }
     }
 }
 

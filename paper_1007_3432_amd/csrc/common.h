@@ -104,17 +104,28 @@ __device__ inline double block_sum(double v) {
 }
 
 // Sum of n deposits of NP values (deposit b at partials[NP*b + k]) in a
-// fixed order: thread t adds deposits t, t+BLOCK, ..., then the block tree.
-// Every caller that sums the same deposits gets the same bits.  Result in
-// thread 0.
+// fixed order: thread t adds deposits t, t+BLOCK, ... (four at a time, the
+// loads issued together), then the block tree.  Every caller that sums the
+// same deposits gets the same bits.  Result in thread 0.  Callers read the
+// deposits after a kernel boundary or a grid barrier, so plain loads see
+// them.
 template <int BLOCK, int NP>
 __device__ inline void reduce_deposits(const double* partials, int n, double (&total)[NP]) {
 #pragma unroll
     for (int k = 0; k < NP; ++k) {
         double s = 0.0;
-        for (int b = threadIdx.x; b < n; b += BLOCK)
-            s += __hip_atomic_load(&partials[NP * b + k], __ATOMIC_RELAXED,
-                                   __HIP_MEMORY_SCOPE_AGENT);
+        int b = threadIdx.x;
+        for (; b + 3 * BLOCK < n; b += 4 * BLOCK) {
+            const double v0 = partials[NP * b + k];
+            const double v1 = partials[NP * (b + BLOCK) + k];
+            const double v2 = partials[NP * (b + 2 * BLOCK) + k];
+            const double v3 = partials[NP * (b + 3 * BLOCK) + k];
+            s += v0;
+            s += v1;
+            s += v2;
+            s += v3;
+        }
+        for (; b < n; b += BLOCK) s += partials[NP * b + k];
         total[k] = block_sum<BLOCK>(s);
     }
 }

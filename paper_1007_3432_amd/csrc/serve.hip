@@ -456,7 +456,7 @@ size_t slot_bytes(const Geom& g) {
     const size_t V = (size_t)g.V;
     const SweepPlan P = plan_sweep(g);
     const int e = elem_tiles(g.V);
-    const size_t parts = sizeof(double) * kMaxNP * (size_t)std::max(P.grid, e);
+    const size_t parts = sizeof(double) * kMaxNP * (size_t)std::max(P.ntiles, e);
     return al256(8 * V) * 2 + al256(4 * V) * 5 + al256(parts);
 }
 
@@ -577,7 +577,7 @@ hub_status start_slot(hub_server* S, int k, Request&& R) {
     sl.q = (float*)take(4 * V);
     sl.xlo = (float*)take(4 * V);
     sl.partials = (double*)take(sizeof(double) * kMaxNP *
-                                (size_t)std::max(sl.P.grid, elem_tiles(g.V)));
+                                (size_t)std::max(sl.P.ntiles, elem_tiles(g.V)));
     HUB_HIP(hipMemcpyAsync(sl.phi, sl.req.phi.data(), 8 * V, hipMemcpyHostToDevice, S->stream));
     const hub_cg_opts& o = S->opts.cg;
     SRV_TRY(serve_slot_init(g, &S->sc_d[k], sl.phi, sl.r, sl.p0, sl.x, sl.xlo, o.tol * o.tol,
@@ -676,7 +676,7 @@ hub_status run_epoch(hub_server* S) {
         d.tiles_y = sl.P.tiles_y;
         d.tiles_z = sl.P.tiles_z;
         d.tc = sl.P.tc;
-        d.sweep_tiles = sl.P.grid;
+        d.sweep_tiles = sl.P.ntiles;
         d.elem_tiles = elem_tiles(d.g.V);
         d.off_sweep = tot_sweep;
         d.off_elem = tot_elem;

@@ -208,123 +208,118 @@ __global__ __launch_bounds__(256) void k_finish_op(Op op, const double* partials
 // ---------------------------------------------------------------------------
 // Fused Q = M^T M sweep for d = 1.
 //
-// A block owns a strip of TX consecutive sites in x and TT consecutive time
-// slices.  It stages the input on slices s0-1 .. s0+TT (sites n0-2 .. n0+w+1)
-// in LDS, keeps A at its own sites in registers, forms y = M in one slice at
-// a time (own sites plus one halo site each side) in a 3-deep LDS ring, and
-// emits z = M^T y for slice s-1 as soon as y_s exists.  HBM traffic is the
-// input and A once (halo rows and columns are shared with neighbouring
-// tiles through L2) plus the outputs.
-template <int TX, int TT>
-constexpr int d1_lds_elems() { return (TT + 2) * (TX + 4) + 3 * (TX + 2); }
+// A tile is a strip of TX consecutive x-sites by TT consecutive time slices;
+// each 64-lane wavefront of the block owns 64 of the x-sites and works on
+// its own, with no LDS and no block barrier: lane i keeps its site's input
+// on slices s0-1 .. s0+TT and A on slices s0 .. s0+TT in registers, takes
+// x-neighbours from lanes i-1 and i+1 (cross-lane shuffles), and the first
+// and last active lanes load the two sites past each end of the wavefront's
+// strip.  Slice by slice it forms y = M in at its site (and the end lanes at
+// the halo site next to it) and then z = M^T y one slice behind.  HBM
+// traffic is the input and A once (the few halo re-reads hit in cache) plus
+// the outputs.  Lanes past a ragged edge and slices past a ragged end
+// re-read the last valid site / slice, so every load is unconditional.
 
-// One tile b of the sweep (block of TX lanes); adds this lane's share of the
-// op's sums to part.  lds: d1_lds_elems<TX, TT>() elements.
+template <int TX, int TT>
+constexpr int d1_lds_elems() { return 0; }
+
+template <class T>
+__device__ __forceinline__ T lane_up(T v) { return __shfl_up(v, 1, 64); }    // from lane-1
+template <class T>
+__device__ __forceinline__ T lane_down(T v) { return __shfl_down(v, 1, 64); }  // from lane+1
+
+// One tile b of the sweep (block of >= TX lanes, TX a multiple of 64); adds
+// this lane's share of the op's sums to part.
 template <class Op, int TX, int TT>
 __device__ __forceinline__ void tile_mtm_d1(const Geom& g, const Op& op, int tiles_x, int b,
-                                            typename Op::acc_t* lds,
+                                            typename Op::acc_t* /*lds*/,
                                             double (&part)[Op::kNP]) {
+    static_assert(TX % 64 == 0, "tile width is whole wavefronts");
     using Acc = typename Op::acc_t;
     using Center = typename Op::center_t;
-    Acc (*xs)[TX + 4] = reinterpret_cast<Acc (*)[TX + 4]>(lds);
-    Acc (*ys)[TX + 2] = reinterpret_cast<Acc (*)[TX + 2]>(lds + (TT + 2) * (TX + 4));
     const int nx = g.nx, nt = g.nt;
     const int tx = b % tiles_x, tt = b / tiles_x;
-    const int n0 = tx * TX, s0 = tt * TT;
-    const int w = min(TX, nx - n0), h = min(TT, nt - s0);
-    const int t = threadIdx.x;
-    const bool own = t < w;
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    if (wave >= TX / 64) return;
+    const int n0 = tx * TX + 64 * wave;            // first site of this wavefront
+    const int w = min(64, nx - n0);                // its active lanes
+    if (w <= 0) return;
+    const int s0 = tt * TT, h = min(TT, nt - s0);
     const Acc kappa = (Acc)g.kappa;
+    const bool own = lane < w;
+    const int site = n0 + (own ? lane : w - 1);
+    const bool left = lane == 0, right = lane == w - 1;
+    // End lanes: h1 = the site next to the strip, h2 = the one after it.
+    const int h1 = wrap1(left ? n0 - 1 : n0 + w, nx);
+    const int h2 = wrap1(left ? n0 - 2 : n0 + w + 1, nx);
 
+    Acc xv[TT + 2], av[TT + 1];
+    Acc x1[TT + 2], x2[TT + 2], a1[TT + 1];
     Center cen[TT];
-    Acc cval[TT];
-    Acc acen[TT + 1];
-    Acc ahalo[TT + 1];
-    Acc xv[TT + 2];
-    Acc hv[TT + 2];
-
-    // x halo lanes 0..3 fill LDS positions 0, 1, w+2, w+3.
-    const int hpos = t < 2 ? t : w + t;
-    const int hsite = wrap1(n0 - 2 + hpos, nx);
-    // A halo lanes 0, 1 hold A at sites n0-1 and n0+w.
-    const int asite = wrap1(t == 0 ? n0 - 1 : n0 + w, nx);
-    // Lanes past a ragged edge and rows past a ragged end re-read the last
-    // valid site / row, so that every load is unconditional and all of them
-    // are in flight together before the first LDS write.
-    const int tc = own ? t : w - 1;
-
 #pragma unroll
     for (int rho = 0; rho < TT + 2; ++rho) {
         const int row = wrap1(s0 - 1 + (rho < h + 2 ? rho : h + 1), nt) * nx;
         if (rho >= 1 && rho <= TT)
-            xv[rho] = op.in_center(row + n0 + tc, cen[rho - 1]);
+            xv[rho] = op.in_center(row + site, cen[rho - 1]);
         else
-            xv[rho] = op.in(row + n0 + tc);
+            xv[rho] = op.in(row + site);
     }
 #pragma unroll
     for (int rho = 0; rho < TT + 1; ++rho) {
-        const int s = wrap1(s0 + (rho <= h ? rho : h), nt);
-        acen[rho] = op.link(s * nx + n0 + tc, s);
+        const int sl = wrap1(s0 + (rho <= h ? rho : h), nt);
+        av[rho] = op.link(sl * nx + site, sl);
     }
-    if (t < 4) {
+    if (left || right) {
 #pragma unroll
         for (int rho = 0; rho < TT + 2; ++rho) {
             const int row = wrap1(s0 - 1 + (rho < h + 2 ? rho : h + 1), nt) * nx;
-            hv[rho] = op.in(row + hsite);
+            x1[rho] = op.in(row + h1);
+            x2[rho] = op.in(row + h2);
         }
-    }
-    if (t < 2) {
 #pragma unroll
         for (int rho = 0; rho < TT + 1; ++rho) {
-            const int s = wrap1(s0 + (rho <= h ? rho : h), nt);
-            ahalo[rho] = op.link(s * nx + asite, s);
+            const int sl = wrap1(s0 + (rho <= h ? rho : h), nt);
+            a1[rho] = op.link(sl * nx + h1, sl);
         }
     }
-#pragma unroll
-    for (int rho = 0; rho < TT + 2; ++rho) {
-        if (own) xs[rho][t + 2] = xv[rho];
-        if (t < 4) xs[rho][hpos] = hv[rho];
-    }
-#pragma unroll
-    for (int rho = 0; rho < TT; ++rho) cval[rho] = xv[rho + 1];
-    __syncthreads();
 
+    Acc y_prev = 0, yh_prev = 0;
 #pragma unroll
     for (int rho = 0; rho < TT + 1; ++rho) {
         if (rho <= h) {
-            Acc* yb = ys[rho % 3];
-            if (own)
-                yb[t + 1] = xs[rho + 1][t + 2] -
-                            kappa * (xs[rho + 1][t + 1] + xs[rho + 1][t + 3]) +
-                            acen[rho] * xs[rho][t + 2];
-            if (t < 2) {
-                const int j = t == 0 ? 0 : w + 1;
-                yb[j] = xs[rho + 1][j + 1] -
-                        kappa * (xs[rho + 1][j] + xs[rho + 1][j + 2]) +
-                        ahalo[rho] * xs[rho][j + 1];
+            // y on slice s0+rho at the lane's site, and at the halo site
+            // next to the end lanes.
+            const Acc xc = xv[rho + 1];
+            Acc xm = lane_up(xc), xp = lane_down(xc);
+            if (left) xm = x1[rho + 1];
+            if (right) xp = x1[rho + 1];
+            const Acc y = xc - kappa * (xm + xp) + av[rho] * xv[rho];
+            Acc yh = 0;
+            if (left || right)
+                yh = x1[rho + 1] - kappa * (x2[rho + 1] + xc) + a1[rho] * x1[rho];
+            if (rho >= 1) {
+                // z on slice s0+rho-1 from y there (and its neighbours) and y here.
+                Acc ym = lane_up(y_prev), yp = lane_down(y_prev);
+                if (left) ym = yh_prev;
+                if (right) yp = yh_prev;
+                const Acc zv = y_prev - kappa * (ym + yp) + av[rho] * y;
+                if (own)
+                    op.out((s0 + rho - 1) * nx + n0 + lane, zv, xv[rho], cen[rho - 1], part);
             }
-            __syncthreads();
-            if (rho >= 1 && own) {
-                const Acc* yp = ys[(rho - 1) % 3];
-                const Acc zv = yp[t + 1] - kappa * (yp[t] + yp[t + 2]) +
-                               acen[rho] * yb[t + 1];
-                op.out((s0 + rho - 1) * nx + n0 + t, zv, cval[rho - 1],
-                       cen[rho - 1], part);
-            }
+            y_prev = y;
+            yh_prev = yh;
         }
     }
 }
 
 template <class Op, int TX, int TT>
-__global__ __launch_bounds__(TX) void k_mtm_d1(Geom g, Op op, int tiles_x,
+__global__ __launch_bounds__(TX) void k_mtm_d1(Geom g, Op op, int tiles_x, int ntiles,
                                                double* partials) {
-    using Acc = typename Op::acc_t;
-    __shared__ Acc lds[d1_lds_elems<TX, TT>()];
     if (op.skip()) return;
     op.begin();
     const int b = xcd_remap(blockIdx.x, gridDim.x);
     double part[Op::kNP] = {};
-    tile_mtm_d1<Op, TX, TT>(g, op, tiles_x, b, lds, part);
+    if (b < ntiles) tile_mtm_d1<Op, TX, TT>(g, op, tiles_x, b, nullptr, part);
     if constexpr (Op::kReduce) deposit<TX, Op::kNP>(part, partials, b);
 }
 

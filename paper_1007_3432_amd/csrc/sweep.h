@@ -34,11 +34,12 @@ struct SweepPlan {
     int variant;   // D1Tile or D3Tile
     int tiles_x;   // d = 1
     int tiles_y, tiles_z, tc;  // d = 3: tiles and slices per block
+    int ntiles;    // tiles of one sweep = deposits of its reductions
     int grid;      // blocks of the sweep kernel (pass 2 when generic)
 };
 
-// Tuning aids: HUB_D1_TILE=<TX>x<TT>, HUB_D3_TILE=<NX>x<TY>x<TZ>,
-// HUB_D3_TC=<slices per block>, HUB_SWEEP=generic.
+// Tuning aids: HUB_D1_TILE=<TX>x<TT>,
+// HUB_D3_TILE=<NX>x<TY>x<TZ>, HUB_D3_TC=<slices per block>, HUB_SWEEP=generic.
 inline const char* env_or_null(const char* k) { return std::getenv(k); }
 
 inline int d1_tile_override() {
@@ -93,7 +94,8 @@ inline SweepPlan plan_sweep(const Geom& g) {
         p.kind = kSweepD1;
         p.variant = v;
         p.tiles_x = ceil_div(g.nx, kD1Shapes[v].tx);
-        p.grid = p.tiles_x * ceil_div(g.nt, kD1Shapes[v].tt);
+        p.ntiles = p.tiles_x * ceil_div(g.nt, kD1Shapes[v].tt);
+        p.grid = p.ntiles;
     } else if (!force_generic() && g.d == 3) {
         int v = d3_tile_override();
         if (v >= 0 && kD3Shapes[v].nx != g.nx) v = -1;
@@ -120,10 +122,11 @@ inline SweepPlan plan_sweep(const Geom& g) {
             tc = env_int("HUB_D3_TC", tc);
             if (tc < 1) tc = 1;
             p.tc = tc;
-            p.grid = tiles * ceil_div(g.nt, tc);
+            p.ntiles = tiles * ceil_div(g.nt, tc);
+            p.grid = p.ntiles;
         }
     }
-    if (p.kind == kSweepGeneric) p.grid = ceil_div(g.V, 256);
+    if (p.kind == kSweepGeneric) p.ntiles = p.grid = ceil_div(g.V, 256);
     p.fused = p.kind != kSweepGeneric;
     return p;
 }
@@ -133,7 +136,7 @@ inline SweepPlan plan_sweep(const Geom& g) {
 inline int max_partials(const Geom& g) {
     const SweepPlan p = plan_sweep(g);
     const int e = elem_tiles(g.V);
-    return kMaxNP * (p.grid > e ? p.grid : e);
+    return kMaxNP * (p.ntiles > e ? p.ntiles : e);
 }
 
 // One sweep: z = Q in, consumed by op.out().  y: scratch of g.V acc_t
@@ -145,7 +148,7 @@ hub_status launch_q(const Geom& g, const SweepPlan& P, const Op& op,
         switch (P.variant) {
 #define HUB_D1_CASE(K, TX, TT)                                                             \
     case K:                                                                                \
-        k_mtm_d1<Op, TX, TT><<<P.grid, TX, 0, st>>>(g, op, P.tiles_x, partials);           \
+        k_mtm_d1<Op, TX, TT><<<P.grid, TX, 0, st>>>(g, op, P.tiles_x, P.ntiles, partials); \
         break;
             HUB_D1_CASE(kD1_256x8, 256, 8)
             HUB_D1_CASE(kD1_128x8, 128, 8)
@@ -188,7 +191,7 @@ hub_status launch_q(const Geom& g, const SweepPlan& P, const Op& op,
     }
     if constexpr (Op::kReduce) {
         if (!partials) return set_error(HUB_E_INVALID, "internal: reduction needs deposits");
-        k_finish_op<Op><<<1, 256, 0, st>>>(op, partials, P.grid);
+        k_finish_op<Op><<<1, 256, 0, st>>>(op, partials, P.ntiles);
     }
     HUB_HIP(hipGetLastError());
     return HUB_OK;
