@@ -32,6 +32,12 @@ HBM_PEAK_GBS = 8000.0
 SWEEP_BYTES_F64 = 24       # per site: x 8 + A 8 + z 8
 CG_ITER_BYTES_F64 = 80     # per site and iteration (phase A 56 + phase B 24)
 
+# HBM bytes one launch of the timed sweep (k_mtm_d1<OpApply<double>, 256, 4>
+# on d=1 2048 x 512) actually moves: rocprofv3 FETCH_SIZE x 2.000 plus
+# WRITE_SIZE x 1.000 per dispatch, each factor calibrated on a 256 MiB copy.
+# Valid only for that kernel and tile; None once either changes.
+SWEEP_TRAFFIC = {"kernel": "k_mtm_d1<OpApply<double>,256,4>", "bytes": 25_617_295}
+
 
 def _args():
     ap = argparse.ArgumentParser()
@@ -323,6 +329,8 @@ def main():
     d1.record()
     torch.cuda.synchronize()
     direct_us = d0.elapsed_time(d1) * 1e3 / 200
+    traffic = (SWEEP_TRAFFIC["bytes"] if SWEEP_TRAFFIC and not os.environ.get("HUB_D1_TILE")
+               and not os.environ.get("HUB_SWEEP") else None)
     cg_stats = [r[2] for r in recs]
     cg_ms = [s["ms"] for s in cg_stats]
     cg_iters = cg_stats[-1]["iters"]
@@ -339,7 +347,9 @@ def main():
                    "d": d, "nx": nx, "nt": nt, "t_hop": 1.0, "dtau": 0.05, "U": -2.0,
                    "mu": 0.0, "parallelism": "single GPU"},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+                     "traffic_unit": "HBM bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, "
+                                     "copy-calibrated)",
                      "kernel": "k_mtm_d1<OpApply<double>> (fused M^T M sweep)",
                      "avg_launch_us": avg_kern_s * 1e6,
                      "bytes_per_launch": SWEEP_BYTES_F64 * V,
