@@ -131,6 +131,44 @@ HUB_API hub_status hub_cg_solve(const hub_lattice* lat, const double* sigma,
                         const double* phi, double* x, const hub_cg_opts* opts,
                         hub_cg_stats* out, void* stream);
 
+/* ---- Chebyshev polynomial preconditioning (Sec. 4.2, Eqs. (13)-(17)) ----
+ * P(Q) = c_{2n} prod_{k=1}^{2n} (Q/scale - z_{2n,k}), with the roots
+ * z_{2n,k} = (1+eps)/2 [1 - cos(2 pi k/(2n+1))] - i sqrt(eps) sin(2 pi k/(2n+1))
+ * and 1/c_{2n} = (1+eps)/2 prod_k ((1+eps)/2 - z_{2n,k}), approximates
+ * scale * Q^{-1} with relative error at most 2((1-sqrt eps)/(1+sqrt eps))^{2n+1}
+ * on the eigenvalues of Q/scale in (eps, 1] (Eq. (16)).  P is positive for
+ * every real argument, so P(Q) is symmetric positive definite whatever the
+ * spectrum; eps and scale only affect how well it approximates. */
+typedef struct {
+    int32_t n;        /* half the polynomial degree, 1 <= n <= 256: P(Q) costs
+                         2n applications of Q */
+    int32_t reserved; /* must be 0 */
+    double eps;       /* lower end of the approximation interval, 0 < eps < 1 */
+    double scale;     /* normalisation of Q; <= 0 selects the bound
+                         (1 + 2 d dtau t + e^{dtau mu}(1 + b))^2 >= lambda_max(Q) */
+} hub_cheb_opts;
+
+/* z = P(Q) r.  links: FP64 time links (hub_links_from_sigma, HUB_F64);
+ * r, z: device FP64[nx^d * nt], distinct.  The conjugate root pairs are
+ * applied as n real quadratic factors, two fused M^T M sweeps each.
+ * Asynchronous on `stream` (allocates one V-vector of workspace
+ * stream-ordered). */
+HUB_API hub_status hub_apply_cheb(const hub_lattice* lat, const double* links,
+                          const double* r, double* z, const hub_cheb_opts* cheb,
+                          void* stream);
+
+/* Solve (M^T M) x = phi by conjugate gradient preconditioned with P(Q)
+ * (Sec. 4.2; the preconditioned CG of Sec. 5), from x = 0, in FP64:
+ * opts->bulk and opts->link must be HUB_F64.  Convergence is decided on
+ * |r| <= tol |phi| and confirmed on the FP64 true residual; a failed
+ * confirmation restarts from the true residual.  stats->iters counts CG
+ * iterations (each costs 2n + 1 applications of Q).  Blocks until done;
+ * returns as hub_cg_solve. */
+HUB_API hub_status hub_pcg_solve(const hub_lattice* lat, const double* sigma,
+                         const double* phi, double* x, const hub_cg_opts* opts,
+                         const hub_cheb_opts* cheb, hub_cg_stats* out,
+                         void* stream);
+
 /* ---- Serving: continuous batching of CG solves from many HMC chains ----
  * A server owns one worker thread, one HIP stream and the resident state of
  * every chain it has seen (field, links, Krylov vectors).  Requests are

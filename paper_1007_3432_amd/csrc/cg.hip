@@ -11,10 +11,12 @@
 // A chunk ends with a fold (x += pending alpha p [+ x_lo]) and an FP64
 // true-residual sweep: always in the mixed solver (the reliable update),
 // only after an iterated convergence in the FP64 solver.
+#include <algorithm>
 #include <cmath>
 #include <cstdlib>
 
 #include "cgtiles.h"
+#include "cheb.h"
 #include "sweep.h"
 
 namespace hub {
@@ -62,6 +64,14 @@ __global__ __launch_bounds__(256) void k_phaseB_finish(CGScalars* sc, const doub
     double tot[1];
     reduce_deposits<256, 1>(partials, n, tot);
     if (threadIdx.x == 0) finish_phaseB(sc, tot[0]);
+}
+
+__global__ __launch_bounds__(256) void k_pcg_phaseB_finish(CGScalars* sc,
+                                                           const double* partials, int n) {
+    if (sc->done != kRunning) return;
+    double tot[1];
+    reduce_deposits<256, 1>(partials, n, tot);
+    if (threadIdx.x == 0) finish_pcg_phaseB(sc, tot[0]);
 }
 
 // x += alpha p (+ x_lo, then x_lo = 0): the pending update, in FP64.
@@ -137,6 +147,11 @@ struct Solver {
     Vec *r, *p0, *p1, *q;
     float* xlo;        // mixed only
     double* yscratch;  // generic sweeps only (holds V doubles)
+    // Chebyshev-preconditioned CG (FP64 only): z = P r before each direction
+    // update; empty cheb means plain CG.
+    std::vector<ChebFactor> cheb;
+    double* z = nullptr;
+    double* w = nullptr;
 
     hub_status fold_and_residual(int mode) {
         k_fold<Vec><<<elem_tiles(g.V), 256, 0, st>>>(sc, mode, x, xlo, p0, p1, g.V);
@@ -156,10 +171,22 @@ struct Solver {
         opA.q = q;
         if constexpr (sizeof(Vec) == 8) opA.x = x; else opA.x = xlo;
         opA.lk = lk;
+        const bool pcg = !cheb.empty();
+        if constexpr (sizeof(Vec) == 8) {
+            if (pcg) opA.r = z;  // p_new = z + beta p_old
+        }
         for (int k = 0; k < iters; ++k) {
+            if constexpr (sizeof(Vec) == 8) {
+                if (pcg)
+                    HUB_TRY(launch_cheb(g, P, A64, sc, r, z, w, yscratch, partials, cheb, true,
+                                        st));
+            }
             HUB_TRY(launch_q(g, P, opA, (Vec*)yscratch, partials, st));
             k_phaseB<Vec><<<elem_tiles(g.V), 256, 0, st>>>(sc, r, q, g.V, partials);
-            k_phaseB_finish<<<1, 256, 0, st>>>(sc, partials, elem_tiles(g.V));
+            if (pcg)
+                k_pcg_phaseB_finish<<<1, 256, 0, st>>>(sc, partials, elem_tiles(g.V));
+            else
+                k_phaseB_finish<<<1, 256, 0, st>>>(sc, partials, elem_tiles(g.V));
         }
         HUB_TRY(fold_and_residual(mixed ? kModeReliable : kModeCheck));
         HUB_HIP(hipMemcpyAsync(snap, sc, sizeof(CGScalars), hipMemcpyDeviceToHost, st));
@@ -222,7 +249,12 @@ hub_status run_solver(Solver<Vec, Lnk>& S, bool mixed, hub_cg_stats* out) {
     k_init_finish<<<1, 256, 0, st>>>(S.sc, S.partials, elem_tiles(g.V), o.tol * o.tol,
                                      mixed ? kReliableDelta * kReliableDelta : 0.0, o.max_iter);
     HUB_HIP(hipGetLastError());
-    const int C = mixed ? o.reliable_every : 50;
+    // Iterations per chunk: about 150 sweeps for plain CG (50 its), the
+    // reliable-update period for mixed CG, and about 200 sweeps (each
+    // iteration 2n + 1) with the preconditioner.
+    const int C = mixed ? o.reliable_every
+                        : (S.cheb.empty() ? 50
+                                          : std::max(2, 200 / (2 * (int)S.cheb.size() + 1)));
     GraphPair G;
     const bool graphs = use_graphs();
     if (graphs) {
@@ -282,8 +314,11 @@ hub_status run_solver(Solver<Vec, Lnk>& S, bool mixed, hub_cg_stats* out) {
 
 }  // namespace
 
-hub_status cg_solve(const Geom& g, const double* sigma, const double* phi, double* x,
-                    const hub_cg_opts& o, hub_cg_stats* out, hipStream_t st) {
+namespace {
+
+hub_status solve(const Geom& g, const double* sigma, const double* phi, double* x,
+                 const hub_cg_opts& o, const hub_cheb_opts* cheb, hub_cg_stats* out,
+                 hipStream_t st) {
     HUB_TRY(g_ctx.ensure());
     const bool mixed = o.bulk == HUB_F32;
     const size_t V = (size_t)g.V;
@@ -301,6 +336,8 @@ hub_status cg_solve(const Geom& g, const double* sigma, const double* phi, doubl
     const size_t o_q = off; off += al(vb * V);
     const size_t o_xlo = off; off += mixed ? al(4 * V) : 0;
     const size_t o_y = off; off += P.fused ? 0 : al(8 * V);
+    const size_t o_z = off; off += cheb ? al(8 * V) : 0;
+    const size_t o_w = off; off += cheb ? al(8 * V) : 0;
     char* ws = nullptr;
     if (hipMallocAsync((void**)&ws, off, st) != hipSuccess) {
         (void)hipGetLastError();
@@ -325,6 +362,12 @@ hub_status cg_solve(const Geom& g, const double* sigma, const double* phi, doubl
             S.q = (double*)(ws + o_q);
             S.xlo = nullptr;
             S.yscratch = P.fused ? nullptr : (double*)(ws + o_y);
+            if (cheb) {
+                const double scale = cheb->scale > 0 ? cheb->scale : cheb_default_scale(g);
+                S.cheb = cheb_factors(cheb->n, cheb->eps, scale);
+                S.z = (double*)(ws + o_z);
+                S.w = (double*)(ws + o_w);
+            }
             result = run_solver(S, false, out);
         } else if (o.link == HUB_F32) {
             Solver<float, Link32> S{g, o, st, P};
@@ -367,6 +410,19 @@ hub_status cg_solve(const Geom& g, const double* sigma, const double* phi, doubl
         return set_error(HUB_E_DEVICE, "hub_cg_solve: %s",
                          hipGetErrorString(e != hipSuccess ? e : e2));
     return result;
+}
+
+}  // namespace
+
+hub_status cg_solve(const Geom& g, const double* sigma, const double* phi, double* x,
+                    const hub_cg_opts& o, hub_cg_stats* out, hipStream_t st) {
+    return solve(g, sigma, phi, x, o, nullptr, out, st);
+}
+
+hub_status pcg_solve(const Geom& g, const double* sigma, const double* phi, double* x,
+                     const hub_cg_opts& o, const hub_cheb_opts& c, hub_cg_stats* out,
+                     hipStream_t st) {
+    return solve(g, sigma, phi, x, o, &c, out, st);
 }
 
 // ---------------------------------------------------------------------------

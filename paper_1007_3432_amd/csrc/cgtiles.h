@@ -116,6 +116,8 @@ __device__ __forceinline__ void finish_init(CGScalars* sc, double total, double 
     sc->iter = 0;
     sc->max_iter = max_iter;
     sc->reliable_updates = 0;
+    sc->rr = total;
+    sc->restart = 1;
     sc->done = !isfinite(total) ? kDoneBreakdown : (total == 0.0 ? kDoneConverged : kRunning);
 }
 
@@ -161,6 +163,21 @@ __device__ __forceinline__ void finish_phaseB(CGScalars* sc, double total) {
     sc->beta = total / sc->rho_prev;
     sc->iter += 1;
     if (total <= sc->tol2phi2 || total < sc->delta2 * sc->rho_ru)
+        sc->done = kDoneIterConverged;
+    else if (sc->iter >= sc->max_iter)
+        sc->done = kDoneMaxIter;
+}
+
+// Preconditioned CG after r.r: iteration count and convergence on |r|^2
+// (rho, beta belong to r.z and are set after the preconditioner).
+__device__ __forceinline__ void finish_pcg_phaseB(CGScalars* sc, double total) {
+    if (!isfinite(total)) {
+        sc->done = kDoneBreakdown;
+        return;
+    }
+    sc->rr = total;
+    sc->iter += 1;
+    if (total <= sc->tol2phi2)
         sc->done = kDoneIterConverged;
     else if (sc->iter >= sc->max_iter)
         sc->done = kDoneMaxIter;

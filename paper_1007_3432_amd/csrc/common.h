@@ -36,11 +36,13 @@ struct CGScalars {
     double rho_ru;     // r.r right after the last reliable update
     double delta2;     // reliable update once rho < delta2 * rho_ru (0: never)
     double pq;         // last p.Qp
+    double rr;         // preconditioned CG: iterated r.r (rho holds r.z)
     int32_t iter;      // iterations completed
     int32_t max_iter;
     int32_t done;      // see kDone* below
     int32_t reliable_updates;
-    int32_t pad[4];
+    int32_t restart;   // preconditioned CG: next beta is 0 (fresh residual)
+    int32_t pad[3];
 };
 
 enum : int32_t {

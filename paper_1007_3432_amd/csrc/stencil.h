@@ -190,7 +190,76 @@ struct OpResidual {
             sc->gamma = gamma;
             sc->rho = rr;
             sc->rho_ru = rr;
+            sc->rr = rr;
+            sc->restart = 1;  // preconditioned CG restarts from the new r
             sc->done = kRunning;
+        }
+    }
+};
+
+// One quadratic factor of the Chebyshev preconditioner (Sec. 4.2, Eq. (13)):
+// a conjugate root pair z, z* of P gives the real factor
+//   (Q/s - z)(Q/s - z*) = c2 Q^2 + c1 Q + c0   (times its normalisation),
+// applied as two sweeps: w = Q v (OpApply-like, OpChebW), then
+// v_out = c2 Q w + c1 w + c0 v (OpChebZ), which reads v only at the site it
+// writes, so v_out may be v.  The last factor of a preconditioned CG step also
+// reduces r.z and sets beta.  With sc == nullptr the ops never skip.
+struct OpChebW {
+    using acc_t = double;
+    using center_t = NoCenter;
+    static constexpr bool kReduce = false;
+    static constexpr int kNP = 1;
+    const CGScalars* sc;
+    const double* v;
+    double* w;
+    Link64 lk;
+    __device__ bool skip() const { return sc && sc->done != kRunning; }
+    __device__ void begin() {}
+    __device__ double link(int i, int s) const { return lk(i, s); }
+    __device__ double in(int i) const { return v[i]; }
+    __device__ double in_center(int i, NoCenter&) const { return v[i]; }
+    __device__ void out(int i, double zv, double, const NoCenter&, double (&)[kNP]) const {
+        w[i] = zv;
+    }
+    __device__ void finish(const double (&)[kNP]) const {}
+};
+
+template <bool kDot>
+struct OpChebZ {
+    using acc_t = double;
+    using center_t = NoCenter;
+    static constexpr bool kReduce = kDot;
+    static constexpr int kNP = 1;
+    CGScalars* sc;
+    const double* w;
+    const double* v;   // factor input (read at the written site only)
+    double* vout;
+    const double* r;   // kDot: residual for r.z
+    double c2, c1, c0;
+    Link64 lk;
+    __device__ bool skip() const { return sc && sc->done != kRunning; }
+    __device__ void begin() {}
+    __device__ double link(int i, int s) const { return lk(i, s); }
+    __device__ double in(int i) const { return w[i]; }
+    __device__ double in_center(int i, NoCenter&) const { return w[i]; }
+    __device__ void out(int i, double zv, double wv, const NoCenter&, double (&part)[kNP]) const {
+        const double o = c2 * zv + c1 * wv + c0 * v[i];
+        vout[i] = o;
+        if constexpr (kDot) part[0] += r[i] * o;
+    }
+    // rho = r.z; beta = 0 after a restart, else r.z / previous r.z.
+    __device__ void finish(const double (&tot)[kNP]) const {
+        if constexpr (kDot) {
+            const double rz = tot[0];
+            if (!(rz > 0.0) || !isfinite(rz)) {
+                sc->done = kDoneBreakdown;
+                return;
+            }
+            sc->beta = sc->restart ? 0.0 : rz / sc->rho;
+            sc->rho_prev = sc->rho;
+            sc->rho = rz;
+            sc->gamma = 1.0;
+            sc->restart = 0;
         }
     }
 };

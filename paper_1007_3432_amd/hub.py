@@ -40,6 +40,11 @@ class CGOpts(ctypes.Structure):
                 ("max_iter", ctypes.c_int32), ("reliable_every", ctypes.c_int32)]
 
 
+class ChebOpts(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int32), ("reserved", ctypes.c_int32), ("eps", ctypes.c_double),
+                ("scale", ctypes.c_double)]
+
+
 class CGStats(ctypes.Structure):
     _fields_ = [("iters", ctypes.c_int32), ("reliable_updates", ctypes.c_int32),
                 ("true_rel_resid", ctypes.c_double), ("ms", ctypes.c_double),
@@ -74,6 +79,12 @@ def cg_opts(bulk: int = F64, link: int | None = None, tol: float = 1e-10,
     return CGOpts(bulk, link, tol, max_iter, reliable_every)
 
 
+def cheb_opts(n: int, eps: float, scale: float = 0.0) -> ChebOpts:
+    """Chebyshev preconditioner of half-degree n on (eps, 1]; scale <= 0 picks
+    the library's bound on the largest eigenvalue of Q."""
+    return ChebOpts(n, 0, eps, scale)
+
+
 _lib = None
 
 
@@ -96,12 +107,16 @@ def load():
     lib.hub_apply_MtM.argtypes = [lp, vp, ctypes.c_int, ctypes.c_int, vp, vp, vp]
     lib.hub_cg_solve.argtypes = [lp, vp, vp, vp, ctypes.POINTER(CGOpts),
                                  ctypes.POINTER(CGStats), vp]
+    lib.hub_apply_cheb.argtypes = [lp, vp, vp, vp, ctypes.POINTER(ChebOpts), vp]
+    lib.hub_pcg_solve.argtypes = [lp, vp, vp, vp, ctypes.POINTER(CGOpts),
+                                  ctypes.POINTER(ChebOpts), ctypes.POINTER(CGStats), vp]
     lib.hub_serve_create.argtypes = [ctypes.POINTER(ServeOpts), ctypes.POINTER(vp)]
     lib.hub_serve_submit.argtypes = [vp, ctypes.c_int32, lp, vp, vp,
                                      ctypes.POINTER(ctypes.c_uint64)]
     lib.hub_serve_poll.argtypes = [vp, ctypes.c_uint64, vp, ctypes.POINTER(CGStats)]
     lib.hub_serve_destroy.argtypes = [vp]
     for f in (lib.hub_links_from_sigma, lib.hub_apply_M, lib.hub_apply_MtM, lib.hub_cg_solve,
+              lib.hub_apply_cheb, lib.hub_pcg_solve,
               lib.hub_serve_create, lib.hub_serve_submit, lib.hub_serve_poll,
               lib.hub_serve_destroy):
         f.restype = ctypes.c_int
@@ -178,6 +193,26 @@ def hub_cg_solve(lat: Lattice, sigma, phi, x, opts: CGOpts, stream=None,
                                  ctypes.byref(opts), ctypes.byref(st), _stream(stream))
     ok = (HUB_OK,) if raise_on_noconv else (HUB_OK, HUB_E_NOCONV)
     _check(status, "hub_cg_solve", ok)
+    return st.as_dict()
+
+
+def hub_apply_cheb(lat: Lattice, links, r, z, cheb: ChebOpts, stream=None) -> None:
+    V = lat.volume
+    _check(load().hub_apply_cheb(ctypes.byref(lat), _dev_ptr(links, F64, V, "links"),
+                                 _dev_ptr(r, F64, V, "r"), _dev_ptr(z, F64, V, "z"),
+                                 ctypes.byref(cheb), _stream(stream)), "hub_apply_cheb")
+
+
+def hub_pcg_solve(lat: Lattice, sigma, phi, x, opts: CGOpts, cheb: ChebOpts, stream=None,
+                  raise_on_noconv: bool = True) -> dict:
+    V = lat.volume
+    st = CGStats()
+    status = load().hub_pcg_solve(ctypes.byref(lat), _dev_ptr(sigma, F64, V, "sigma"),
+                                  _dev_ptr(phi, F64, V, "phi"), _dev_ptr(x, F64, V, "x"),
+                                  ctypes.byref(opts), ctypes.byref(cheb), ctypes.byref(st),
+                                  _stream(stream))
+    ok = (HUB_OK,) if raise_on_noconv else (HUB_OK, HUB_E_NOCONV)
+    _check(status, "hub_pcg_solve", ok)
     return st.as_dict()
 
 

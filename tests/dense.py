@@ -103,3 +103,14 @@ def lanczos_condition(alphas, betas) -> float:
     off = np.sqrt(b) / a[:-1]
     ev = scipy.linalg.eigvalsh_tridiagonal(diag, off)
     return float(ev[-1] / ev[0])
+
+
+def cheb_closed_form(lam, n: int, eps: float):
+    """P(l) of Eq. (13) from the identity 1 - l P(l) = T_{2n+1}(u) / T_{2n+1}(u(0)),
+    u = (2 l - 1 - eps) / (1 - eps); valid for l > 0."""
+    from numpy.polynomial import chebyshev
+    m = 2 * n + 1
+    coef = [0.0] * m + [1.0]
+    u = (2.0 * np.asarray(lam) - 1.0 - eps) / (1.0 - eps)
+    u0 = -(1.0 + eps) / (1.0 - eps)
+    return (1.0 - chebyshev.chebval(u, coef) / chebyshev.chebval(u0, coef)) / lam

@@ -18,7 +18,7 @@ def lib():
 def test_header_declares_the_api():
     names = set(hub.declared_symbols())
     assert {"hub_links_from_sigma", "hub_apply_M", "hub_apply_MtM", "hub_cg_solve",
-            "hub_serve_create", "hub_serve_submit", "hub_serve_poll",
+            "hub_apply_cheb", "hub_pcg_solve", "hub_serve_create", "hub_serve_submit", "hub_serve_poll",
             "hub_serve_destroy", "hub_last_error"} <= names
 
 
@@ -74,6 +74,36 @@ def test_cg_options_validated(lib):
         s = lib.hub_cg_solve(ctypes.byref(lat), ctypes.c_void_p(16), ctypes.c_void_p(32),
                              ctypes.c_void_p(48), ctypes.byref(opts), ctypes.byref(st), None)
         assert s == hub.HUB_E_INVALID
+
+
+@pytest.mark.parametrize("cheb", [hub.ChebOpts(0, 0, 0.01, 0.0), hub.ChebOpts(257, 0, 0.01, 0.0),
+                                  hub.ChebOpts(4, 1, 0.01, 0.0), hub.ChebOpts(4, 0, 0.0, 0.0),
+                                  hub.ChebOpts(4, 0, 1.0, 0.0),
+                                  hub.ChebOpts(4, 0, 0.01, math.inf)])
+def test_cheb_options_validated(lib, cheb):
+    lat = hub.lattice(1, 8, 8)
+    assert lib.hub_apply_cheb(ctypes.byref(lat), ctypes.c_void_p(16), ctypes.c_void_p(32),
+                              ctypes.c_void_p(48), ctypes.byref(cheb), None) == hub.HUB_E_INVALID
+    st = hub.CGStats()
+    assert lib.hub_pcg_solve(ctypes.byref(lat), ctypes.c_void_p(16), ctypes.c_void_p(32),
+                             ctypes.c_void_p(48), ctypes.byref(hub.cg_opts()),
+                             ctypes.byref(cheb), ctypes.byref(st), None) == hub.HUB_E_INVALID
+    assert lib.hub_apply_cheb(ctypes.byref(lat), ctypes.c_void_p(16), ctypes.c_void_p(32),
+                              None, ctypes.byref(hub.cheb_opts(4, 0.01)), None) == hub.HUB_E_INVALID
+    assert lib.hub_apply_cheb(ctypes.byref(lat), ctypes.c_void_p(16), ctypes.c_void_p(32),
+                              ctypes.c_void_p(32), ctypes.byref(hub.cheb_opts(4, 0.01)),
+                              None) == hub.HUB_E_INVALID
+
+
+def test_pcg_requires_fp64(lib):
+    lat = hub.lattice(1, 8, 8)
+    st = hub.CGStats()
+    for opts in (hub.cg_opts(bulk=hub.F32), hub.cg_opts(bulk=hub.F32, link=hub.F16)):
+        assert lib.hub_pcg_solve(ctypes.byref(lat), ctypes.c_void_p(16), ctypes.c_void_p(32),
+                                 ctypes.c_void_p(48), ctypes.byref(opts),
+                                 ctypes.byref(hub.cheb_opts(4, 0.01)), ctypes.byref(st),
+                                 None) == hub.HUB_E_INVALID
+        assert "F64" in hub.last_error()
 
 
 def test_last_error_empty_after_success_path_is_thread_local(lib):

@@ -15,7 +15,6 @@ import math
 
 import numpy as np
 import pytest
-from numpy.polynomial import chebyshev
 
 import oracle
 from oracle import Lattice
@@ -25,11 +24,7 @@ from tests import dense
 
 def _p_closed(lam, n, eps):
     """P(l) from the Chebyshev closed form (valid for l > 0)."""
-    m = 2 * n + 1
-    coef = [0.0] * m + [1.0]
-    u = (2.0 * lam - 1.0 - eps) / (1.0 - eps)
-    u0 = -(1.0 + eps) / (1.0 - eps)
-    return (1.0 - chebyshev.chebval(u, coef) / chebyshev.chebval(u0, coef)) / lam
+    return dense.cheb_closed_form(lam, n, eps)
 
 
 def _p_product(lam, n, eps):
