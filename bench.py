@@ -32,11 +32,11 @@ HBM_PEAK_GBS = 8000.0
 SWEEP_BYTES_F64 = 24       # per site: x 8 + A 8 + z 8
 CG_ITER_BYTES_F64 = 80     # per site and iteration (phase A 56 + phase B 24)
 
-# HBM bytes one launch of the timed sweep (k_mtm_d1<OpApply<double>, 256, 4>
+# HBM bytes one launch of the timed sweep (k_mtm_d1p<OpApply<double>, 512, 2>
 # on d=1 2048 x 512) actually moves: rocprofv3 FETCH_SIZE x 2.000 plus
 # WRITE_SIZE x 1.000 per dispatch, each factor calibrated on a 256 MiB copy.
 # Valid only for that kernel and tile; None once either changes.
-SWEEP_TRAFFIC = {"kernel": "k_mtm_d1<OpApply<double>,256,4>", "bytes": 25_617_295}
+SWEEP_TRAFFIC = {"kernel": "k_mtm_d1p<OpApply<double>,512,2>", "bytes": 25_612_871}
 
 
 def _args():
@@ -109,6 +109,33 @@ def cg_compare(hub, inputs, shape, link_mixed, reps=1):
     out["mixed"]["rel_diff_vs_fp64_solution"] = float(diff)
     out["speedup_mixed_vs_fp64"] = out["fp64"]["ms_per_solve"] / out["mixed"]["ms_per_solve"]
     return out
+
+
+def pcg_compare(hub, inputs, shape, grid):
+    """FP64 CG vs Chebyshev-preconditioned FP64 CG on one workload, over a grid
+    of (n, eps); the paper gives neither, so every point is reported."""
+    import torch
+    d, nx, nt = shape
+    lat = hub.lattice(d, nx, nt)
+    sigma, eta = inputs.sigma_eta(d, nx, nt, seed=0)
+    sig_d, eta_d = _dev(sigma), _dev(eta)
+    links = torch.empty(lat.volume, dtype=torch.float64, device="cuda:0")
+    hub.hub_links_from_sigma(lat, sig_d, links, hub.F64)
+    phi = torch.empty_like(eta_d)
+    hub.hub_apply_M(lat, links, hub.F64, hub.F64, eta_d, phi, 1)
+    x = torch.empty_like(phi)
+    opts = hub.cg_opts(hub.F64, max_iter=1000000)
+    st = hub.hub_cg_solve(lat, sig_d, phi, x, opts)
+    cg = {"ms": st["ms"], "iters": st["iters"], "q_applications": st["iters"]}
+    runs = []
+    for n, eps in grid:
+        st = hub.hub_pcg_solve(lat, sig_d, phi, x, opts, hub.cheb_opts(n, eps))
+        runs.append({"n": n, "eps": eps, "ms": st["ms"], "iters": st["iters"],
+                     "q_applications": st["iters"] * (2 * n + 1),
+                     "true_rel_resid": st["true_rel_resid"]})
+    best = min(runs, key=lambda r: r["ms"])
+    return {"cg_fp64": cg, "pcg_fp64": runs, "best": best,
+            "speedup_best_pcg_vs_cg": cg["ms"] / best["ms"]}
 
 
 def serve_bench(hub, inputs, engine: int, seconds: float, think_mean_s: float | None,
@@ -329,7 +356,7 @@ def main():
     d1.record()
     torch.cuda.synchronize()
     direct_us = d0.elapsed_time(d1) * 1e3 / 200
-    traffic = (SWEEP_TRAFFIC["bytes"] if SWEEP_TRAFFIC and not os.environ.get("HUB_D1_TILE")
+    traffic = (SWEEP_TRAFFIC["bytes"] if SWEEP_TRAFFIC and not os.environ.get("HUB_D1P_TILE")
                and not os.environ.get("HUB_SWEEP") else None)
     cg_stats = [r[2] for r in recs]
     cg_ms = [s["ms"] for s in cg_stats]
@@ -350,7 +377,7 @@ def main():
                      "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                      "traffic_unit": "HBM bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, "
                                      "copy-calibrated)",
-                     "kernel": "k_mtm_d1<OpApply<double>> (fused M^T M sweep)",
+                     "kernel": "k_mtm_d1p<OpApply<double>,512,2> (fused M^T M sweep, two sites per lane)",
                      "avg_launch_us": avg_kern_s * 1e6,
                      "bytes_per_launch": SWEEP_BYTES_F64 * V,
                      "timing": ("HIP events around the sweeps launched one by one, / calls"
@@ -372,6 +399,9 @@ def main():
     if not a.no_detail:
         line["detail"]["cg_c2_d3_16x160"] = cg_compare(hub, inputs, (3, 16, 160), hub.F32)
         line["detail"]["cg_c3_d3_32x256"] = cg_compare(hub, inputs, (3, 32, 256), hub.F16)
+        grid = [(n, e) for n in (4, 8, 16, 32) for e in (1e-4, 4e-4, 1.6e-3)]
+        line["detail"]["pcg_c1_d1_2048x512"] = pcg_compare(hub, inputs, (1, 2048, 512), grid)
+        line["detail"]["pcg_c2_d3_16x160"] = pcg_compare(hub, inputs, (3, 16, 160), grid)
     if a.serve:
         line["detail"]["serve_poisson_200_per_s"] = serve_bench(hub, inputs, a.engine,
                                                                a.serve_seconds, 64 / 200)

@@ -147,7 +147,7 @@ hub_status launch_cheb(const Geom& g, const SweepPlan& P, const double* A64, CGS
 
 hub_status cheb_apply(const Geom& g, const double* links, const double* r, double* z,
                       const hub_cheb_opts& c, hipStream_t st) {
-    const SweepPlan P = plan_sweep(g);
+    const SweepPlan P = plan_sweep(g, true);
     const double scale = c.scale > 0 ? c.scale : cheb_default_scale(g);
     const std::vector<ChebFactor> f = cheb_factors(c.n, c.eps, scale);
     const size_t vb = ((size_t)g.V * 8 + 255) & ~size_t(255);

@@ -43,7 +43,7 @@ hub_status launch_apply_MtM(const Geom& g, const void* links, hub_dtype link,
 size_t mtm_scratch_bytes(const Geom& g, hub_dtype vec);
 
 // True when Q sweeps on this geometry use the fused single-pass kernel.
-bool mtm_fused(const Geom& g);
+bool mtm_fused(const Geom& g, hub_dtype vec);
 
 // Blocking CG solve (arguments already validated).
 hub_status cg_solve(const Geom& g, const double* sigma, const double* phi,

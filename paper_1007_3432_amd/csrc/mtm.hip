@@ -5,16 +5,16 @@ namespace hub {
 
 Link16 make_link16(const Geom& g, const void* links);
 
-bool mtm_fused(const Geom& g) { return plan_sweep(g).fused; }
+bool mtm_fused(const Geom& g, hub_dtype vec) { return plan_sweep(g, vec == HUB_F64).fused; }
 
 size_t mtm_scratch_bytes(const Geom& g, hub_dtype vec) {
-    return mtm_fused(g) ? 0 : (size_t)g.V * dtype_size(vec);
+    return mtm_fused(g, vec) ? 0 : (size_t)g.V * dtype_size(vec);
 }
 
 template <class Acc, class Vec, class Lnk>
 static hub_status mtm_t(const Geom& g, Lnk lk, const void* x, void* z, void* scratch,
                         hipStream_t st) {
-    const SweepPlan P = plan_sweep(g);
+    const SweepPlan P = plan_sweep(g, sizeof(Vec) == 8);
     OpApply<Acc, Vec, Lnk> op{(const Vec*)x, (Vec*)z, lk};
     Acc* y = (Acc*)scratch;
     bool own = false;

@@ -454,7 +454,7 @@ size_t chain_bytes(const Geom& g, hub_dtype link) {
 
 size_t slot_bytes(const Geom& g) {
     const size_t V = (size_t)g.V;
-    const SweepPlan P = plan_sweep(g);
+    const SweepPlan P = plan_sweep(g, false);
     const int e = elem_tiles(g.V);
     const size_t parts = sizeof(double) * kMaxNP * (size_t)std::max(P.ntiles, e);
     return al256(8 * V) * 2 + al256(4 * V) * 5 + al256(parts);
@@ -563,7 +563,7 @@ hub_status start_slot(hub_server* S, int k, Request&& R) {
     SRV_TRY(upload_chain(S, c, sl.req));
     const Geom& g = sl.req.g;
     const size_t V = (size_t)g.V;
-    sl.P = plan_sweep(g);
+    sl.P = plan_sweep(g, false);
     sl.bytes = slot_bytes(g);
     HUB_HIP(hipMallocAsync((void**)&sl.mem, sl.bytes, S->stream));
     S->resident += sl.bytes;
@@ -873,7 +873,7 @@ hub_status hub_serve_submit(hub_server* srv, int32_t chain_id, const hub_lattice
         if (!phi_host) return set_error(HUB_E_INVALID, "phi_host is NULL");
         Geom g;
         SRV_TRY(make_geom(lat, &g));
-        const SweepPlan P = plan_sweep(g);
+        const SweepPlan P = plan_sweep(g, false);
         if (!serve_supported(P))
             return set_error(HUB_E_INVALID,
                              "serving steps d=1 lattices and d=3 lattices with nx in {8, 16, "

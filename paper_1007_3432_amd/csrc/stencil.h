@@ -10,6 +10,8 @@
 // coefficient (negative except on slice 0, the antiperiodic wrap).
 #pragma once
 
+#include <type_traits>
+
 #include "common.h"
 
 namespace hub {
@@ -17,9 +19,23 @@ namespace hub {
 // ---------------------------------------------------------------------------
 // Link readers: A_{n,s} at linear index i (slice s).
 
+// Two consecutive FP64 values (sites i, i+1 with i even) moved as one
+// 16-byte access; the pair sweep of d = 1 uses these.
+struct D2 {
+    double a, b;
+};
+__device__ __forceinline__ D2 ld2(const double* p) {
+    const double2 w = *reinterpret_cast<const double2*>(p);
+    return {w.x, w.y};
+}
+__device__ __forceinline__ void st2(double* p, double a, double b) {
+    *reinterpret_cast<double2*>(p) = make_double2(a, b);
+}
+
 struct Link64 {
     const double* a;
     __device__ double operator()(int i, int) const { return a[i]; }
+    __device__ D2 pair(int i, int) const { return ld2(a + i); }
 };
 
 struct Link32 {
@@ -50,6 +66,9 @@ struct Link16 {
 //   in_center(i, c)          same, keeping what out() needs in c
 //   out(i, z, v, c, part)    consume z = (Q in)_i, v = in_i; add to part[]
 //   finish(total)            thread 0 of the last block: reduced totals
+//   kPair                    FP64 ops that also provide in2 / in_center2 /
+//                            link2 / out2, the same for sites i, i+1 (i even)
+//                            with 16-byte accesses (the d = 1 pair sweep)
 // No op writes a buffer that in() reads, so tiles may run in any order.
 
 struct NoCenter {};
@@ -79,6 +98,15 @@ struct OpApply {
         z[i] = (Vec)zv;
     }
     __device__ void finish(const double (&)[kNP]) const {}
+    static constexpr bool kPair = sizeof(Acc) == 8 && sizeof(Vec) == 8 &&
+                                  std::is_same<Lnk, Link64>::value;
+    __device__ D2 in2(int i) const { return ld2((const double*)x + i); }
+    __device__ D2 in_center2(int i, NoCenter&, NoCenter&) const { return in2(i); }
+    __device__ D2 link2(int i, int s) const { return lk.pair(i, s); }
+    __device__ void out2(int i, D2 zv, D2, const NoCenter&, const NoCenter&,
+                         double (&)[kNP]) const {
+        st2((double*)z + i, zv.a, zv.b);
+    }
 };
 
 // CG direction update fused with q = Q p (Sec. 4.1, CG on Q):
@@ -124,6 +152,28 @@ struct OpPhaseA {
         x[i] = (XVec)((Acc)x[i] + alpha * c.pold);
         part[0] += (double)v * (double)zv;
     }
+    static constexpr bool kPair = sizeof(Acc) == 8 && sizeof(Vec) == 8 && sizeof(XVec) == 8 &&
+                                  std::is_same<Lnk, Link64>::value;
+    __device__ D2 in2(int i) const {
+        const D2 rv = ld2((const double*)r + i), pv = ld2((const double*)pold + i);
+        return {gamma * rv.a + beta * pv.a, gamma * rv.b + beta * pv.b};
+    }
+    __device__ D2 in_center2(int i, center_t& c0, center_t& c1) const {
+        const D2 rv = ld2((const double*)r + i), pv = ld2((const double*)pold + i);
+        c0.pold = pv.a;
+        c1.pold = pv.b;
+        return {gamma * rv.a + beta * pv.a, gamma * rv.b + beta * pv.b};
+    }
+    __device__ D2 link2(int i, int s) const { return lk.pair(i, s); }
+    __device__ void out2(int i, D2 zv, D2 v, const center_t& c0, const center_t& c1,
+                         double (&part)[kNP]) const {
+        st2((double*)pnew + i, v.a, v.b);
+        st2((double*)q + i, zv.a, zv.b);
+        const D2 xv = ld2((const double*)x + i);
+        st2((double*)x + i, xv.a + alpha * c0.pold, xv.b + alpha * c1.pold);
+        part[0] += v.a * zv.a;
+        part[0] += v.b * zv.b;
+    }
     __device__ void finish(const double (&tot)[kNP]) const {
         const double pq = tot[0];
         sc->pq = pq;
@@ -168,6 +218,20 @@ struct OpResidual {
         r[i] = rd;
         part[0] += d * d;
         part[1] += (double)rd * (double)pcur[i];
+    }
+    static constexpr bool kPair = sizeof(RVec) == 8;
+    __device__ D2 in2(int i) const { return ld2(x + i); }
+    __device__ D2 in_center2(int i, NoCenter&, NoCenter&) const { return ld2(x + i); }
+    __device__ D2 link2(int i, int s) const { return lk.pair(i, s); }
+    __device__ void out2(int i, D2 zv, D2, const NoCenter&, const NoCenter&,
+                         double (&part)[kNP]) const {
+        const D2 f = ld2(phi + i), pc = ld2((const double*)pcur + i);
+        const double d0 = f.a - zv.a, d1 = f.b - zv.b;
+        st2((double*)r + i, d0, d1);
+        part[0] += d0 * d0;
+        part[0] += d1 * d1;
+        part[1] += d0 * pc.a;
+        part[1] += d1 * pc.b;
     }
     __device__ void finish(const double (&tot)[kNP]) const {
         const double rr = tot[0];
@@ -222,6 +286,14 @@ struct OpChebW {
         w[i] = zv;
     }
     __device__ void finish(const double (&)[kNP]) const {}
+    static constexpr bool kPair = true;
+    __device__ D2 in2(int i) const { return ld2(v + i); }
+    __device__ D2 in_center2(int i, NoCenter&, NoCenter&) const { return ld2(v + i); }
+    __device__ D2 link2(int i, int s) const { return lk.pair(i, s); }
+    __device__ void out2(int i, D2 zv, D2, const NoCenter&, const NoCenter&,
+                         double (&)[kNP]) const {
+        st2(w + i, zv.a, zv.b);
+    }
 };
 
 template <bool kDot>
@@ -246,6 +318,22 @@ struct OpChebZ {
         const double o = c2 * zv + c1 * wv + c0 * v[i];
         vout[i] = o;
         if constexpr (kDot) part[0] += r[i] * o;
+    }
+    static constexpr bool kPair = true;
+    __device__ D2 in2(int i) const { return ld2(w + i); }
+    __device__ D2 in_center2(int i, NoCenter&, NoCenter&) const { return ld2(w + i); }
+    __device__ D2 link2(int i, int s) const { return lk.pair(i, s); }
+    __device__ void out2(int i, D2 zv, D2 wv, const NoCenter&, const NoCenter&,
+                         double (&part)[kNP]) const {
+        const D2 vv = ld2(v + i);
+        const double o0 = c2 * zv.a + c1 * wv.a + c0 * vv.a;
+        const double o1 = c2 * zv.b + c1 * wv.b + c0 * vv.b;
+        st2(vout + i, o0, o1);
+        if constexpr (kDot) {
+            const D2 rv = ld2(r + i);
+            part[0] += rv.a * o0;
+            part[0] += rv.b * o1;
+        }
     }
     // rho = r.z; beta = 0 after a restart, else r.z / previous r.z.
     __device__ void finish(const double (&tot)[kNP]) const {
@@ -317,7 +405,10 @@ __device__ __forceinline__ void tile_mtm_d1(const Geom& g, const Op& op, int til
     const Acc kappa = (Acc)g.kappa;
     const bool own = lane < w;
     const int site = n0 + (own ? lane : w - 1);
-    const bool left = lane == 0, right = lane == w - 1;
+    // A one-site strip (nx = 1 mod 64) lends lane 1 the right end: it loads
+    // the right halo and lane 0 takes those values by shuffle.
+    const bool solo = w == 1;
+    const bool left = lane == 0, right = lane == (solo ? 1 : w - 1);
     // End lanes: h1 = the site next to the strip, h2 = the one after it.
     const int h1 = wrap1(left ? n0 - 1 : n0 + w, nx);
     const int h2 = wrap1(left ? n0 - 2 : n0 + w + 1, nx);
@@ -362,6 +453,10 @@ __device__ __forceinline__ void tile_mtm_d1(const Geom& g, const Op& op, int til
             Acc xm = lane_up(xc), xp = lane_down(xc);
             if (left) xm = x1[rho + 1];
             if (right) xp = x1[rho + 1];
+            if (solo) {
+                const Acc xr = lane_down(x1[rho + 1]);
+                if (left) xp = xr;
+            }
             const Acc y = xc - kappa * (xm + xp) + av[rho] * xv[rho];
             Acc yh = 0;
             if (left || right)
@@ -371,6 +466,10 @@ __device__ __forceinline__ void tile_mtm_d1(const Geom& g, const Op& op, int til
                 Acc ym = lane_up(y_prev), yp = lane_down(y_prev);
                 if (left) ym = yh_prev;
                 if (right) yp = yh_prev;
+                if (solo) {
+                    const Acc yr = lane_down(yh_prev);
+                    if (left) yp = yr;
+                }
                 const Acc zv = y_prev - kappa * (ym + yp) + av[rho] * y;
                 if (own)
                     op.out((s0 + rho - 1) * nx + n0 + lane, zv, xv[rho], cen[rho - 1], part);
@@ -390,6 +489,127 @@ __global__ __launch_bounds__(TX) void k_mtm_d1(Geom g, Op op, int tiles_x, int n
     double part[Op::kNP] = {};
     if (b < ntiles) tile_mtm_d1<Op, TX, TT>(g, op, tiles_x, b, nullptr, part);
     if constexpr (Op::kReduce) deposit<TX, Op::kNP>(part, partials, b);
+}
+
+// Whether an op provides the pair accessors (kPair, default false).
+template <class Op, class = void>
+struct op_has_pair : std::false_type {};
+template <class Op>
+struct op_has_pair<Op, std::void_t<decltype(Op::kPair)>> : std::bool_constant<Op::kPair> {};
+
+// ---------------------------------------------------------------------------
+// Pair variant of the d = 1 sweep (FP64 ops, nx even).
+//
+// As tile_mtm_d1, but each lane owns two adjacent x-sites, so a wavefront
+// covers 128 sites and every access of the owned sites is one 16-byte load
+// or store.  Inside a pair the x-neighbours are the lane's own values; across
+// pairs one cross-lane shuffle per direction and slice suffices (the left
+// neighbour of site 2l is the second site of lane l-1).  With nx even every
+// row starts at an even index, so pairs stay 16-byte aligned.
+template <class Op, int TX, int TT>
+__device__ __forceinline__ void tile_mtm_d1p(const Geom& g, const Op& op, int tiles_x, int b,
+                                             double (&part)[Op::kNP]) {
+    static_assert(TX % 128 == 0, "tile width is whole pair wavefronts");
+    using Center = typename Op::center_t;
+    const int nx = g.nx, nt = g.nt;
+    const int tx = b % tiles_x, tt = b / tiles_x;
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    if (wave >= TX / 128) return;
+    const int n0 = tx * TX + 128 * wave;            // first site of this wavefront
+    const int w = min(128, nx - n0);                // its sites (even)
+    if (w <= 0) return;
+    const int np = w >> 1;                          // its active lanes
+    const int s0 = tt * TT, h = min(TT, nt - s0);
+    const double kappa = g.kappa;
+    const bool own = lane < np;
+    const int site = n0 + 2 * (own ? lane : np - 1);
+    // A one-pair strip (nx = 2 mod 128) lends lane 1 the right end, as in
+    // tile_mtm_d1.
+    const bool solo = np == 1;
+    const bool left = lane == 0, right = lane == (solo ? 1 : np - 1);
+    const int h1 = wrap1(left ? n0 - 1 : n0 + w, nx);
+    const int h2 = wrap1(left ? n0 - 2 : n0 + w + 1, nx);
+
+    D2 xv[TT + 2], av[TT + 1];
+    double x1[TT + 2], x2[TT + 2], a1[TT + 1];
+    Center cen[TT][2];
+#pragma unroll
+    for (int rho = 0; rho < TT + 2; ++rho) {
+        const int row = wrap1(s0 - 1 + (rho < h + 2 ? rho : h + 1), nt) * nx;
+        if (rho >= 1 && rho <= TT)
+            xv[rho] = op.in_center2(row + site, cen[rho - 1][0], cen[rho - 1][1]);
+        else
+            xv[rho] = op.in2(row + site);
+    }
+#pragma unroll
+    for (int rho = 0; rho < TT + 1; ++rho) {
+        const int sl = wrap1(s0 + (rho <= h ? rho : h), nt);
+        av[rho] = op.link2(sl * nx + site, sl);
+    }
+    if (left || right) {
+#pragma unroll
+        for (int rho = 0; rho < TT + 2; ++rho) {
+            const int row = wrap1(s0 - 1 + (rho < h + 2 ? rho : h + 1), nt) * nx;
+            x1[rho] = op.in(row + h1);
+            x2[rho] = op.in(row + h2);
+        }
+#pragma unroll
+        for (int rho = 0; rho < TT + 1; ++rho) {
+            const int sl = wrap1(s0 + (rho <= h ? rho : h), nt);
+            a1[rho] = op.link(sl * nx + h1, sl);
+        }
+    }
+
+    D2 y_prev{0.0, 0.0};
+    double yh_prev = 0.0;
+#pragma unroll
+    for (int rho = 0; rho < TT + 1; ++rho) {
+        if (rho <= h) {
+            const D2 xc = xv[rho + 1];
+            double xm = lane_up(xc.b), xp = lane_down(xc.a);
+            if (left) xm = x1[rho + 1];
+            if (right) xp = x1[rho + 1];
+            if (solo) {
+                const double xr = lane_down(x1[rho + 1]);
+                if (left) xp = xr;
+            }
+            D2 y;
+            y.a = xc.a - kappa * (xm + xc.b) + av[rho].a * xv[rho].a;
+            y.b = xc.b - kappa * (xc.a + xp) + av[rho].b * xv[rho].b;
+            double yh = 0.0;
+            if (left || right)
+                yh = x1[rho + 1] - kappa * (x2[rho + 1] + (left ? xc.a : xc.b)) +
+                     a1[rho] * x1[rho];
+            if (rho >= 1) {
+                double ym = lane_up(y_prev.b), yp = lane_down(y_prev.a);
+                if (left) ym = yh_prev;
+                if (right) yp = yh_prev;
+                if (solo) {
+                    const double yr = lane_down(yh_prev);
+                    if (left) yp = yr;
+                }
+                D2 zv;
+                zv.a = y_prev.a - kappa * (ym + y_prev.b) + av[rho].a * y.a;
+                zv.b = y_prev.b - kappa * (y_prev.a + yp) + av[rho].b * y.b;
+                if (own)
+                    op.out2((s0 + rho - 1) * nx + site, zv, xv[rho], cen[rho - 1][0],
+                            cen[rho - 1][1], part);
+            }
+            y_prev = y;
+            yh_prev = yh;
+        }
+    }
+}
+
+template <class Op, int TX, int TT>
+__global__ __launch_bounds__(TX / 2) void k_mtm_d1p(Geom g, Op op, int tiles_x, int ntiles,
+                                                    double* partials) {
+    if (op.skip()) return;
+    op.begin();
+    const int b = xcd_remap(blockIdx.x, gridDim.x);
+    double part[Op::kNP] = {};
+    if (b < ntiles) tile_mtm_d1p<Op, TX, TT>(g, op, tiles_x, b, part);
+    if constexpr (Op::kReduce) deposit<TX / 2, Op::kNP>(part, partials, b);
 }
 
 // ---------------------------------------------------------------------------

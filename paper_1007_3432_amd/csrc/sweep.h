@@ -28,10 +28,16 @@ static constexpr D3Shape kD3Shapes[kD3_Count] = {
 
 enum SweepKind { kSweepD1 = 0, kSweepD3, kSweepGeneric };
 
+// Pair tiles of the d = 1 sweep (FP64, nx even): TX sites x TT slices.
+enum D1PTile { kD1P_512x2 = 0, kD1P_256x2, kD1P_128x2, kD1P_512x4, kD1P_512x1, kD1P_Count };
+static constexpr D1Shape kD1PShapes[kD1P_Count] = {
+    {512, 2}, {256, 2}, {128, 2}, {512, 4}, {512, 1}};
+
 struct SweepPlan {
     int kind;      // SweepKind
     bool fused;    // single pass (kSweepD1 / kSweepD3)
-    int variant;   // D1Tile or D3Tile
+    bool pair;     // kSweepD1 with the pair tile (variant is a D1PTile)
+    int variant;   // D1Tile, D1PTile or D3Tile
     int tiles_x;   // d = 1
     int tiles_y, tiles_z, tc;  // d = 3: tiles and slices per block
     int ntiles;    // tiles of one sweep = deposits of its reductions
@@ -71,6 +77,21 @@ inline int d3_tile_override() {
     return v;
 }
 
+inline int d1p_tile_override() {
+    static int v = [] {
+        const char* e = env_or_null("HUB_D1P_TILE");
+        if (!e) return -1;
+        if (std::strcmp(e, "off") == 0) return -2;
+        for (int k = 0; k < kD1P_Count; ++k) {
+            char buf[32];
+            std::snprintf(buf, sizeof(buf), "%dx%d", kD1PShapes[k].tx, kD1PShapes[k].tt);
+            if (std::strcmp(buf, e) == 0) return k;
+        }
+        return -1;
+    }();
+    return v;
+}
+
 inline int env_int(const char* k, int dflt) {
     const char* e = env_or_null(k);
     return e ? std::atoi(e) : dflt;
@@ -84,11 +105,23 @@ inline bool force_generic() {
     return v;
 }
 
-inline SweepPlan plan_sweep(const Geom& g) {
+// f64: the sweep's ops are FP64 throughout, so the pair tile may serve d = 1.
+inline SweepPlan plan_sweep(const Geom& g, bool f64) {
     SweepPlan p{};
     p.kind = kSweepGeneric;
     p.variant = -1;
-    if (!force_generic() && g.d == 1) {
+    p.pair = false;
+    const int pv = d1p_tile_override();
+    if (!force_generic() && g.d == 1 && f64 && g.nx % 2 == 0 && pv != -2) {
+        int v = pv;
+        if (v < 0) v = g.nx >= 512 ? kD1P_512x2 : (g.nx >= 256 ? kD1P_256x2 : kD1P_128x2);
+        p.kind = kSweepD1;
+        p.pair = true;
+        p.variant = v;
+        p.tiles_x = ceil_div(g.nx, kD1PShapes[v].tx);
+        p.ntiles = p.tiles_x * ceil_div(g.nt, kD1PShapes[v].tt);
+        p.grid = p.ntiles;
+    } else if (!force_generic() && g.d == 1) {
         int v = d1_tile_override();
         if (v < 0) v = g.nx >= 256 ? kD1_256x4 : (g.nx >= 128 ? kD1_128x4 : kD1_64x4);
         p.kind = kSweepD1;
@@ -134,9 +167,11 @@ inline SweepPlan plan_sweep(const Geom& g) {
 // Doubles of deposit space any reduction over this geometry may need:
 // kMaxNP sums for each tile of the largest grid (sweep or element-wise).
 inline int max_partials(const Geom& g) {
-    const SweepPlan p = plan_sweep(g);
+    const SweepPlan p = plan_sweep(g, false), q = plan_sweep(g, true);
     const int e = elem_tiles(g.V);
-    return kMaxNP * (p.ntiles > e ? p.ntiles : e);
+    int m = p.ntiles > e ? p.ntiles : e;
+    m = q.ntiles > m ? q.ntiles : m;
+    return kMaxNP * m;
 }
 
 // One sweep: z = Q in, consumed by op.out().  y: scratch of g.V acc_t
@@ -144,7 +179,27 @@ inline int max_partials(const Geom& g) {
 template <class Op>
 hub_status launch_q(const Geom& g, const SweepPlan& P, const Op& op,
                     typename Op::acc_t* y, double* partials, hipStream_t st) {
-    if (P.kind == kSweepD1) {
+    if (P.kind == kSweepD1 && P.pair) {
+        if constexpr (op_has_pair<Op>::value) {
+            switch (P.variant) {
+#define HUB_D1P_CASE(K, TX, TT)                                                         \
+    case K:                                                                             \
+        k_mtm_d1p<Op, TX, TT><<<P.grid, TX / 2, 0, st>>>(g, op, P.tiles_x, P.ntiles,     \
+                                                          partials);                     \
+        break;
+                HUB_D1P_CASE(kD1P_512x2, 512, 2)
+                HUB_D1P_CASE(kD1P_256x2, 256, 2)
+                HUB_D1P_CASE(kD1P_128x2, 128, 2)
+                HUB_D1P_CASE(kD1P_512x4, 512, 4)
+                HUB_D1P_CASE(kD1P_512x1, 512, 1)
+#undef HUB_D1P_CASE
+                default:
+                    return set_error(HUB_E_INVALID, "internal: bad d=1 pair tile variant");
+            }
+        } else {
+            return set_error(HUB_E_INVALID, "internal: op has no pair access");
+        }
+    } else if (P.kind == kSweepD1) {
         switch (P.variant) {
 #define HUB_D1_CASE(K, TX, TT)                                                             \
     case K:                                                                                \

@@ -22,6 +22,7 @@ pytestmark = pytest.mark.gpu
 SHAPES = [
     (1, 32, 64), (1, 2, 2), (1, 2, 3), (1, 3, 2), (1, 5, 7), (1, 37, 9), (1, 64, 8),
     (1, 255, 17), (1, 256, 16), (1, 300, 20), (1, 1000, 13), (1, 2048, 512),
+    (1, 65, 6), (1, 129, 5), (1, 130, 6), (1, 258, 4), (1, 642, 3),
     (2, 2, 2), (2, 5, 4), (2, 8, 6),
     (3, 2, 2), (3, 3, 5), (3, 4, 6), (3, 8, 80), (3, 5, 3), (3, 16, 160),
 ]
