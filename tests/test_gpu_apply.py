@@ -137,6 +137,32 @@ def test_apply_full_size_c3_fp64():
     assert hubtest.rel_err(z_d.cpu().numpy(), oracle.apply_MtM(olat, A, x)) <= 1e-13
 
 
+@pytest.mark.parametrize("vec", [hub.F64, hub.F32], ids=["f64", "f32"])
+def test_apply_d3_nx64(vec):
+    """d=3, 64^3 x 4 (1 048 576 sites): the default 64 x 4 x 4 tile of the
+    fused d = 3 sweep, element-wise against the oracle."""
+    d, nx, nt = 3, 64, 4
+    olat, lat = _lat(d, nx, nt)
+    hubtest.log_case(f"apply d3 nx64 vec={vec}")
+    sigma, _ = inputs.sigma_eta(d, nx, nt, seed=11)
+    x = inputs.random_vector(olat.volume, 12)
+    A = oracle.links(olat, sigma)
+    if vec == hub.F64:
+        A_d, x_d, xr, tol = hubtest.to_dev(A), hubtest.to_dev(x), x, 1e-13
+    else:
+        A_d = hubtest.to_dev(A.astype(np.float32))
+        x_d = hubtest.to_dev(x.astype(np.float32))
+        xr = x.astype(np.float32).astype(np.float64)
+        A = A.astype(np.float32).astype(np.float64)
+        tol = 2e-6
+    z_d = hubtest.empty(lat.volume, vec)
+    hub.hub_apply_MtM(lat, A_d, vec, vec, x_d, z_d)
+    z = z_d.double().cpu().numpy()
+    z_ref = oracle.apply_MtM(olat, A, xr)
+    assert hubtest.rel_err(z, z_ref) <= tol
+    assert np.max(np.abs(z - z_ref)) <= tol * np.max(np.abs(z_ref))
+
+
 def test_special_cases():
     """U = 0 (free fermions), t = 0 (decoupled sites), large mu."""
     for kw in (dict(U=0.0), dict(t_hop=0.0), dict(mu=2.0), dict(dtau=0.2, U=-7.915)):

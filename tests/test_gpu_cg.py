@@ -110,12 +110,33 @@ def test_cg_full_size_c1_fp64():
     assert _true_resid(olat, A, phi, x) <= 1.1 * TOL
 
 
-def test_cg_full_size_c3_mixed_f16():
+@pytest.mark.parametrize("prec", ["f64", "f16"])
+def test_cg_full_size_c3(prec):
+    """d=3 32^3 x 256 (8.4M sites): FP64 CG and mixed CG with FP16 links, each
+    checked by the oracle's true residual."""
     olat, lat, sigma, A, phi = _problem(3, 32, 256)
-    hubtest.log_case("cg c3 full f16")
-    x, st = _solve(lat, sigma, phi, hub.cg_opts(hub.F32, hub.F16))
+    hubtest.log_case(f"cg c3 full {prec}")
+    opts = hub.cg_opts(hub.F64) if prec == "f64" else hub.cg_opts(hub.F32, hub.F16)
+    x, st = _solve(lat, sigma, phi, opts)
     assert st["status"] == "HUB_OK"
     assert _true_resid(olat, A, phi, x) <= 1.1 * TOL
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_cg_d3_nx64(prec):
+    """d=3, 64^3 x 4 on the default 64 x 4 x 4 tile (FP64 links for the
+    residual, bulk links per precision): oracle true residual and distance to
+    the oracle's solution."""
+    olat, lat, sigma, A, phi = _problem(3, 64, 4)
+    hubtest.log_case(f"cg d3 nx64 {prec}")
+    x_o, res_o, (al, be) = oracle.cg(olat, A, phi, tol=TOL, record=True)
+    assert res_o.converged
+    kappa = dense.lanczos_condition(al, be)
+    opts = hub.cg_opts(hub.F64) if prec == "f64" else hub.cg_opts(hub.F32, hub.F32)
+    x, st = _solve(lat, sigma, phi, opts)
+    assert st["status"] == "HUB_OK"
+    assert _true_resid(olat, A, phi, x) <= 1.1 * TOL
+    assert hubtest.rel_err(x, x_o) <= 4 * kappa * TOL
 
 
 # --- failure handling (all forced from the host; every kernel exits normally)
