@@ -157,6 +157,22 @@ HUB_API hub_status hub_apply_cheb(const hub_lattice* lat, const double* links,
                           const double* r, double* z, const hub_cheb_opts* cheb,
                           void* stream);
 
+/* z = P(Q) r exactly as hub_apply_cheb (same kernels, same factor order,
+ * bitwise the same result), for callers that cannot allocate: code under HIP
+ * graph capture, serving loops, harnesses that forbid allocation.  The
+ * workspace (one FP64 vector of nx^d * nt elements, two when the lattice has
+ * no fused sweep: d = 2, or d = 3 with nx not in {8, 16, 32, 64}) lives in a
+ * fixed 64 MiB device array that the library holds on every GPU it runs on
+ * until the process ends; no device or host memory is allocated by the call.
+ * Lattices whose workspace exceeds 64 MiB (more than 8 388 608 sites, or
+ * 4 194 304 without a fused sweep) are rejected with HUB_E_NOMEM before
+ * anything is launched.  All calls on one GPU share that array: calls that
+ * overlap in time on one GPU (other streams, other threads) race and must be
+ * serialised by the caller.  Asynchronous on `stream`. */
+HUB_API hub_status hub_apply_cheb_noalloc(const hub_lattice* lat, const double* links,
+                                  const double* r, double* z, const hub_cheb_opts* cheb,
+                                  void* stream);
+
 /* Solve (M^T M) x = phi by conjugate gradient preconditioned with P(Q)
  * (Sec. 4.2; the preconditioned CG of Sec. 5), from x = 0, in FP64:
  * opts->bulk and opts->link must be HUB_F64.  Convergence is decided on

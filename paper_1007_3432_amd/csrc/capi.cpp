@@ -157,6 +157,22 @@ hub_status hub_apply_cheb(const hub_lattice* lat, const double* links, const dou
     HUB_GUARD_END
 }
 
+hub_status hub_apply_cheb_noalloc(const hub_lattice* lat, const double* links, const double* r,
+                                  double* z, const hub_cheb_opts* cheb, void* stream) {
+    HUB_GUARD_BEGIN
+    clear_error();
+    Geom g;
+    HUB_TRY(make_geom(lat, &g));
+    HUB_TRY(check_cheb(cheb));
+    HUB_TRY(check_vec_ptr(links, "links"));
+    HUB_TRY(check_vec_ptr(r, "r"));
+    HUB_TRY(check_vec_ptr(z, "z"));
+    if ((const void*)r == (const void*)z || (const void*)z == (const void*)links)
+        return set_error(HUB_E_INVALID, "z aliases an input");
+    return cheb_apply_noalloc(g, links, r, z, *cheb, (hipStream_t)stream);
+    HUB_GUARD_END
+}
+
 hub_status hub_pcg_solve(const hub_lattice* lat, const double* sigma, const double* phi,
                          double* x, const hub_cg_opts* opts, const hub_cheb_opts* cheb,
                          hub_cg_stats* out, void* stream) {

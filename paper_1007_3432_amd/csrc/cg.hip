@@ -178,8 +178,8 @@ struct Solver {
         for (int k = 0; k < iters; ++k) {
             if constexpr (sizeof(Vec) == 8) {
                 if (pcg)
-                    HUB_TRY(launch_cheb(g, P, A64, sc, r, z, w, yscratch, partials, cheb, true,
-                                        st));
+                    HUB_TRY(launch_cheb(g, P, A64, sc, r, z, w, yscratch, partials, cheb.data(),
+                                        (int)cheb.size(), true, st));
             }
             HUB_TRY(launch_q(g, P, opA, (Vec*)yscratch, partials, st));
             k_phaseB<Vec><<<elem_tiles(g.V), 256, 0, st>>>(sc, r, q, g.V, partials);

@@ -19,6 +19,7 @@
 // n = 128.  The order is computed once per (n, eps) and cached.
 #include <algorithm>
 #include <cmath>
+#include <cstdint>
 #include <map>
 #include <mutex>
 #include <vector>
@@ -29,51 +30,66 @@ namespace hub {
 
 namespace {
 
-// Greedy factor order for (n, eps) in k = 1 .. n, cached per process.
-std::vector<int> factor_order(int n, double eps) {
-    static std::mutex mu;
-    static std::map<std::pair<int, double>, std::vector<int>> cache;
-    {
-        std::lock_guard<std::mutex> lk(mu);
-        auto it = cache.find({n, eps});
-        if (it != cache.end()) return it->second;
-    }
+// Greedy factor order for (n, eps), n <= kMaxChebN, in k = 1 .. n.  Computed
+// without heap allocation (fixed static work arrays under a lock) and kept
+// in a fixed-size table, so that every caller -- including the
+// no-allocation entry point -- gets it without allocating.
+constexpr int kMaxChebN = 256;
+constexpr int kGrid = 1024;
+constexpr int kOrderCache = 64;
+
+struct OrderEntry {
+    int n;
+    double eps;
+    uint16_t order[kMaxChebN];
+};
+
+std::mutex g_order_mu;
+OrderEntry g_orders[kOrderCache];
+int g_orders_used = 0, g_orders_next = 0;
+double g_lf[kMaxChebN * kGrid];  // log f_k(lambda_i), under g_order_mu
+double g_lam[kGrid], g_total[kGrid], g_pre[kGrid];
+
+void factor_order(int n, double eps, uint16_t* order) {
+    std::lock_guard<std::mutex> lk(g_order_mu);
+    for (int e = 0; e < g_orders_used; ++e)
+        if (g_orders[e].n == n && g_orders[e].eps == eps) {
+            std::copy(g_orders[e].order, g_orders[e].order + n, order);
+            return;
+        }
     const double pi = 3.14159265358979323846;
     const double h = 0.5 * (1.0 + eps);
     // Grid: 512 points uniform on [0, 1] and 512 log-spaced on [eps/64, 1].
-    std::vector<double> lam;
-    for (int i = 0; i < 512; ++i) lam.push_back(i / 511.0);
+    for (int i = 0; i < 512; ++i) g_lam[i] = i / 511.0;
     const double l0 = std::log(eps / 64.0);
-    for (int i = 0; i < 512; ++i) lam.push_back(std::exp(l0 * (1.0 - i / 511.0)));
-    const int L = (int)lam.size();
+    for (int i = 0; i < 512; ++i) g_lam[512 + i] = std::exp(l0 * (1.0 - i / 511.0));
+    const int L = kGrid;
     // log f_k(l) of the normalised pair factors, and their sum.
-    std::vector<double> lf((size_t)n * L), total(L, 0.0);
+    std::fill(g_total, g_total + L, 0.0);
     for (int k = 1; k <= n; ++k) {
         const double th = 2.0 * pi * k / (2 * n + 1);
         const double a = h * (1.0 - std::cos(th));
         const double bi = std::sqrt(eps) * std::sin(th);
         const double norm = 1.0 / ((h - a) * (h - a) + bi * bi);
         for (int i = 0; i < L; ++i) {
-            const double v = std::log(((lam[i] - a) * (lam[i] - a) + bi * bi) * norm);
-            lf[(size_t)(k - 1) * L + i] = v;
-            total[i] += v;
+            const double v = std::log(((g_lam[i] - a) * (g_lam[i] - a) + bi * bi) * norm);
+            g_lf[(size_t)(k - 1) * L + i] = v;
+            g_total[i] += v;
         }
     }
-    std::vector<double> pre(L, 0.0);
-    std::vector<char> used(n, 0);
-    std::vector<int> order;
-    order.reserve(n);
+    std::fill(g_pre, g_pre + L, 0.0);
+    bool used[kMaxChebN] = {};
     for (int step = 0; step < n; ++step) {
         int best = -1;
         double best_m = 0.0;
         for (int k = 0; k < n; ++k) {
             if (used[k]) continue;
-            const double* f = &lf[(size_t)k * L];
+            const double* f = &g_lf[(size_t)k * L];
             double mp = 0.0, ms = -1e300;
             for (int i = 0; i < L; ++i) {
-                const double p = pre[i] + f[i];
+                const double p = g_pre[i] + f[i];
                 mp = std::max(mp, p);
-                ms = std::max(ms, total[i] - p);
+                ms = std::max(ms, g_total[i] - p);
             }
             const double m = mp + ms;
             if (best < 0 || m < best_m) {
@@ -81,38 +97,45 @@ std::vector<int> factor_order(int n, double eps) {
                 best_m = m;
             }
         }
-        used[best] = 1;
-        order.push_back(best + 1);
-        for (int i = 0; i < L; ++i) pre[i] += lf[(size_t)best * L + i];
+        used[best] = true;
+        order[step] = (uint16_t)(best + 1);
+        for (int i = 0; i < L; ++i) g_pre[i] += g_lf[(size_t)best * L + i];
     }
-    std::lock_guard<std::mutex> lk(mu);
-    cache[{n, eps}] = order;
-    return order;
+    OrderEntry& e = g_orders[g_orders_next];
+    g_orders_next = (g_orders_next + 1) % kOrderCache;
+    if (g_orders_used < kOrderCache) ++g_orders_used;
+    e.n = n;
+    e.eps = eps;
+    std::copy(order, order + n, e.order);
 }
 
 }  // namespace
 
-std::vector<ChebFactor> cheb_factors(int n, double eps, double scale) {
+void cheb_factors(int n, double eps, double scale, ChebFactor* f) {
     const double pi = 3.14159265358979323846;
     const double h = 0.5 * (1.0 + eps);
-    const std::vector<int> order = factor_order(n, eps);
-    std::vector<ChebFactor> f;
-    f.reserve(n);
-    for (int k : order) {
+    uint16_t order[kMaxChebN];
+    factor_order(n, eps, order);
+    for (int j = 0; j < n; ++j) {
+        const int k = order[j];
         const double th = 2.0 * pi * k / (2 * n + 1);
         const double a = h * (1.0 - std::cos(th));       // Re z_{2n,k}
         const double bi = std::sqrt(eps) * std::sin(th);  // -Im z_{2n,k}
         const double norm = 1.0 / ((h - a) * (h - a) + bi * bi);
-        ChebFactor c;
+        ChebFactor& c = f[j];
         c.c2 = norm / (scale * scale);
         c.c1 = -2.0 * a * norm / scale;
         c.c0 = (a * a + bi * bi) * norm;
-        f.push_back(c);
     }
     // The remaining constant of c_{2n}: 1 / h.
-    f.back().c2 /= h;
-    f.back().c1 /= h;
-    f.back().c0 /= h;
+    f[n - 1].c2 /= h;
+    f[n - 1].c1 /= h;
+    f[n - 1].c0 /= h;
+}
+
+std::vector<ChebFactor> cheb_factors(int n, double eps, double scale) {
+    std::vector<ChebFactor> f((size_t)n);
+    cheb_factors(n, eps, scale, f.data());
     return f;
 }
 
@@ -125,9 +148,8 @@ double cheb_default_scale(const Geom& g) {
 
 hub_status launch_cheb(const Geom& g, const SweepPlan& P, const double* A64, CGScalars* sc,
                        const double* r, double* z, double* w, double* yscratch,
-                       double* partials, const std::vector<ChebFactor>& f, bool dot,
+                       double* partials, const ChebFactor* f, int n, bool dot,
                        hipStream_t st) {
-    const int n = (int)f.size();
     for (int j = 0; j < n; ++j) {
         const double* v = j == 0 ? r : z;
         OpChebW opw{sc, v, w, Link64{A64}};
@@ -149,7 +171,8 @@ hub_status cheb_apply(const Geom& g, const double* links, const double* r, doubl
                       const hub_cheb_opts& c, hipStream_t st) {
     const SweepPlan P = plan_sweep(g, true);
     const double scale = c.scale > 0 ? c.scale : cheb_default_scale(g);
-    const std::vector<ChebFactor> f = cheb_factors(c.n, c.eps, scale);
+    ChebFactor f[kMaxChebN];
+    cheb_factors(c.n, c.eps, scale, f);
     const size_t vb = ((size_t)g.V * 8 + 255) & ~size_t(255);
     char* ws = nullptr;
     const size_t bytes = vb * (P.fused ? 1 : 2);
@@ -159,11 +182,77 @@ hub_status cheb_apply(const Geom& g, const double* links, const double* r, doubl
     }
     double* w = (double*)ws;
     double* y = P.fused ? nullptr : (double*)(ws + vb);
-    const hub_status s = launch_cheb(g, P, links, nullptr, r, z, w, y, nullptr, f, false, st);
+    const hub_status s = launch_cheb(g, P, links, nullptr, r, z, w, y, nullptr, f, c.n, false, st);
     const hipError_t e = hipFreeAsync(ws, st);
     if (s != HUB_OK) return s;
     if (e != hipSuccess) return set_error(HUB_E_DEVICE, "hipFreeAsync: %s", hipGetErrorString(e));
     return HUB_OK;
+}
+
+// ---------------------------------------------------------------------------
+// No-allocation variant: the workspace (w, and y for two-pass plans) lives in
+// a fixed array of kNoAllocBytes that every GPU running the library holds
+// until the process ends.  Host code never passes the array's name to a
+// kernel: its device address on the current GPU is looked up once per device
+// (hipGetSymbolAddress) and kept in g_scratch_ptr.  All calls on one GPU
+// share the array, so calls that overlap in time on one GPU race.  Nothing in
+// it must start at zero: every sweep writes its whole output before the next
+// one reads it.
+
+static __device__ __align__(256) double scratch[kNoAllocBytes / sizeof(double)];
+
+namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+double* g_scratch_ptr[kMaxDevices] = {};
+
+hub_status noalloc_scratch(double** out) {
+    int dev = 0;
+    HUB_HIP(hipGetDevice(&dev));
+    if (dev < 0 || dev >= kMaxDevices)
+        return set_error(HUB_E_DEVICE, "device ordinal %d beyond the %d supported", dev,
+                         kMaxDevices);
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void* p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p)
+            return set_error(HUB_E_DEVICE, "hipGetSymbolAddress(scratch) on device %d: %s", dev,
+                             hipGetErrorString(e));
+        g_scratch_ptr[dev] = (double*)p;
+    }
+    *out = g_scratch_ptr[dev];
+    return HUB_OK;
+}
+
+}  // namespace
+
+size_t cheb_noalloc_bytes(const Geom& g) {
+    const SweepPlan P = plan_sweep(g, true);
+    const size_t vb = ((size_t)g.V * 8 + 255) & ~size_t(255);
+    return vb * (P.fused ? 1 : 2);
+}
+
+hub_status cheb_apply_noalloc(const Geom& g, const double* links, const double* r, double* z,
+                              const hub_cheb_opts& c, hipStream_t st) {
+    const size_t need = cheb_noalloc_bytes(g);
+    if (need > kNoAllocBytes)
+        return set_error(HUB_E_NOMEM,
+                         "hub_apply_cheb_noalloc: %d sites need %zu bytes of workspace, the "
+                         "fixed array holds %zu",
+                         g.V, need, kNoAllocBytes);
+    double* ws = nullptr;
+    hub_status s = noalloc_scratch(&ws);
+    if (s != HUB_OK) return s;
+    const SweepPlan P = plan_sweep(g, true);
+    const double scale = c.scale > 0 ? c.scale : cheb_default_scale(g);
+    ChebFactor f[kMaxChebN];
+    cheb_factors(c.n, c.eps, scale, f);
+    const size_t vb = ((size_t)g.V * 8 + 255) & ~size_t(255);
+    double* w = ws;
+    double* y = P.fused ? nullptr : (double*)((char*)ws + vb);
+    return launch_cheb(g, P, links, nullptr, r, z, w, y, nullptr, f, c.n, false, st);
 }
 
 }  // namespace hub

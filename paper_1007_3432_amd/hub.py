@@ -108,6 +108,7 @@ def load():
     lib.hub_cg_solve.argtypes = [lp, vp, vp, vp, ctypes.POINTER(CGOpts),
                                  ctypes.POINTER(CGStats), vp]
     lib.hub_apply_cheb.argtypes = [lp, vp, vp, vp, ctypes.POINTER(ChebOpts), vp]
+    lib.hub_apply_cheb_noalloc.argtypes = [lp, vp, vp, vp, ctypes.POINTER(ChebOpts), vp]
     lib.hub_pcg_solve.argtypes = [lp, vp, vp, vp, ctypes.POINTER(CGOpts),
                                   ctypes.POINTER(ChebOpts), ctypes.POINTER(CGStats), vp]
     lib.hub_serve_create.argtypes = [ctypes.POINTER(ServeOpts), ctypes.POINTER(vp)]
@@ -116,7 +117,7 @@ def load():
     lib.hub_serve_poll.argtypes = [vp, ctypes.c_uint64, vp, ctypes.POINTER(CGStats)]
     lib.hub_serve_destroy.argtypes = [vp]
     for f in (lib.hub_links_from_sigma, lib.hub_apply_M, lib.hub_apply_MtM, lib.hub_cg_solve,
-              lib.hub_apply_cheb, lib.hub_pcg_solve,
+              lib.hub_apply_cheb, lib.hub_apply_cheb_noalloc, lib.hub_pcg_solve,
               lib.hub_serve_create, lib.hub_serve_submit, lib.hub_serve_poll,
               lib.hub_serve_destroy):
         f.restype = ctypes.c_int
@@ -201,6 +202,14 @@ def hub_apply_cheb(lat: Lattice, links, r, z, cheb: ChebOpts, stream=None) -> No
     _check(load().hub_apply_cheb(ctypes.byref(lat), _dev_ptr(links, F64, V, "links"),
                                  _dev_ptr(r, F64, V, "r"), _dev_ptr(z, F64, V, "z"),
                                  ctypes.byref(cheb), _stream(stream)), "hub_apply_cheb")
+
+
+def hub_apply_cheb_noalloc(lat: Lattice, links, r, z, cheb: ChebOpts, stream=None) -> None:
+    V = lat.volume
+    _check(load().hub_apply_cheb_noalloc(ctypes.byref(lat), _dev_ptr(links, F64, V, "links"),
+                                         _dev_ptr(r, F64, V, "r"), _dev_ptr(z, F64, V, "z"),
+                                         ctypes.byref(cheb), _stream(stream)),
+           "hub_apply_cheb_noalloc")
 
 
 def hub_pcg_solve(lat: Lattice, sigma, phi, x, opts: CGOpts, cheb: ChebOpts, stream=None,

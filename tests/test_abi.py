@@ -18,7 +18,7 @@ def lib():
 def test_header_declares_the_api():
     names = set(hub.declared_symbols())
     assert {"hub_links_from_sigma", "hub_apply_M", "hub_apply_MtM", "hub_cg_solve",
-            "hub_apply_cheb", "hub_pcg_solve", "hub_serve_create", "hub_serve_submit", "hub_serve_poll",
+            "hub_apply_cheb", "hub_apply_cheb_noalloc", "hub_pcg_solve", "hub_serve_create", "hub_serve_submit", "hub_serve_poll",
             "hub_serve_destroy", "hub_last_error"} <= names
 
 
@@ -93,6 +93,18 @@ def test_cheb_options_validated(lib, cheb):
     assert lib.hub_apply_cheb(ctypes.byref(lat), ctypes.c_void_p(16), ctypes.c_void_p(32),
                               ctypes.c_void_p(32), ctypes.byref(hub.cheb_opts(4, 0.01)),
                               None) == hub.HUB_E_INVALID
+
+
+def test_cheb_noalloc_rejects_oversize_before_launch(lib):
+    """More sites than the fixed 64 MiB workspace holds: HUB_E_NOMEM from the
+    host-side check, before any device call."""
+    for lat in (hub.lattice(1, 4096, 2050),          # 8 396 800 sites, fused plan
+                hub.lattice(2, 1448, 3)):            # 6 290 112 sites, two-pass plan
+        s = lib.hub_apply_cheb_noalloc(ctypes.byref(lat), ctypes.c_void_p(16),
+                                       ctypes.c_void_p(32), ctypes.c_void_p(48),
+                                       ctypes.byref(hub.cheb_opts(4, 0.01)), None)
+        assert s == hub.HUB_E_NOMEM
+        assert "64 MiB" in hub.last_error() or "workspace" in hub.last_error()
 
 
 def test_pcg_requires_fp64(lib):
