@@ -24,6 +24,11 @@ Parity status of each function (the pins live under ``tests/``):
                      scalar polynomial
   cheb_scale         pinned: bound >= largest eigenvalue of Q (dense)
   pcg                pinned: dense solve, fewer iterations than CG
+  force              pinned: central finite differences of S_p(sigma) =
+                     phi^T Q^{-1} phi with Q dense (numpy solve)
+  md                 pinned: reversibility (pi -> -pi retraces the path),
+                     energy error O(eps^2), S_p = eta.eta for phi = M^T eta
+  hmc                pinned: Metropolis decision and field restore on reject
 """
 from __future__ import annotations
 
@@ -76,6 +81,26 @@ class Lattice:
                         self.U, self.mu)
 
 
+class _MDResult(ctypes.Structure):
+    _fields_ = [("h_start", ctypes.c_double), ("h_end", ctypes.c_double),
+                ("solves", ctypes.c_int32), ("cg_iters", ctypes.c_int32),
+                ("accepted", ctypes.c_int32), ("failed", ctypes.c_int32)]
+
+
+@dataclass
+class MDResult:
+    h_start: float
+    h_end: float
+    solves: int
+    cg_iters: int
+    accepted: bool
+    failed: bool
+
+    @property
+    def delta_h(self) -> float:
+        return self.h_end - self.h_start
+
+
 @dataclass
 class CGResult:
     iters: int
@@ -122,6 +147,14 @@ def _load():
     lib.oracle_pcg.argtypes = [lp, dp, dp, dp, ctypes.c_double, ctypes.c_int32, ctypes.c_double,
                                ctypes.c_int32, ctypes.c_double, ctypes.POINTER(_CGResult)]
     lib.oracle_pcg.restype = ctypes.c_int
+    lib.oracle_force.argtypes = [lp, dp, dp, dp]
+    lib.oracle_force.restype = None
+    lib.oracle_md.argtypes = [lp, dp, dp, dp, ctypes.c_double, ctypes.c_int32, ctypes.c_double,
+                              ctypes.c_int32, ctypes.POINTER(_MDResult)]
+    lib.oracle_md.restype = ctypes.c_int
+    lib.oracle_hmc.argtypes = [lp, dp, dp, dp, ctypes.c_double, ctypes.c_double, ctypes.c_int32,
+                               ctypes.c_double, ctypes.c_int32, ctypes.POINTER(_MDResult)]
+    lib.oracle_hmc.restype = ctypes.c_int
     lib.oracle_set_threads.argtypes = [ctypes.c_int]
     lib.oracle_set_threads.restype = ctypes.c_int
     _lib = lib
@@ -263,3 +296,47 @@ def pcg(lat: Lattice, A, phi, n: int, eps: float, tol: float = 1e-10,
         raise MemoryError("oracle_pcg: allocation failed")
     return x, CGResult(res.iters, bool(res.converged), bool(res.breakdown),
                        res.restarts, res.true_rel_resid, res.iter_rel_resid)
+
+
+# --- Hybrid Monte Carlo, phi-algorithm (Sec. 4.1) ---
+
+def _md_out(r: _MDResult) -> MDResult:
+    return MDResult(r.h_start, r.h_end, r.solves, r.cg_iters, bool(r.accepted), bool(r.failed))
+
+
+def force(lat: Lattice, sigma, x) -> np.ndarray:
+    """dS_p/dsigma at every site for x = Q^{-1} phi (S_p = phi^T Q^{-1} phi)."""
+    sigma = _vec(sigma, lat.volume)
+    x = _vec(x, lat.volume)
+    F = np.empty(lat.volume)
+    _load().oracle_force(ctypes.byref(lat._c()), _ptr(sigma), _ptr(x), _ptr(F))
+    return F
+
+
+def md(lat: Lattice, sigma, pi, phi, eps: float, n_steps: int, tol: float = 1e-10,
+       max_iter: int = 200000):
+    """Leapfrog MD trajectory; returns (sigma_end, pi_end, MDResult)."""
+    s = _vec(sigma, lat.volume).copy()
+    p = _vec(pi, lat.volume).copy()
+    phi = _vec(phi, lat.volume)
+    r = _MDResult()
+    rc = _load().oracle_md(ctypes.byref(lat._c()), _ptr(s), _ptr(p), _ptr(phi), float(eps),
+                           int(n_steps), float(tol), int(max_iter), ctypes.byref(r))
+    if rc < 0:
+        raise MemoryError("oracle_md: allocation failed")
+    return s, p, _md_out(r)
+
+
+def hmc(lat: Lattice, sigma, eta, pi0, u: float, eps: float, n_steps: int,
+        tol: float = 1e-10, max_iter: int = 200000):
+    """One HMC trajectory (heatbath phi = M^T eta, MD, Metropolis with u);
+    returns (sigma_out, MDResult)."""
+    s = _vec(sigma, lat.volume).copy()
+    eta = _vec(eta, lat.volume)
+    pi0 = _vec(pi0, lat.volume)
+    r = _MDResult()
+    rc = _load().oracle_hmc(ctypes.byref(lat._c()), _ptr(s), _ptr(eta), _ptr(pi0), float(u),
+                            float(eps), int(n_steps), float(tol), int(max_iter), ctypes.byref(r))
+    if rc < 0:
+        raise MemoryError("oracle_hmc: allocation failed")
+    return s, _md_out(r)

@@ -392,3 +392,138 @@ int oracle_set_threads(int n) {
     return 1;
 #endif
 }
+
+/* ---------------------------------------------------------------------------
+ * Hybrid Monte Carlo, phi-algorithm (Sec. 4.1).
+ *
+ * (det M)^2 = det Q = Int Dphi exp(-S_p) with S_p = phi^T Q^{-1} phi, Q = M^T M
+ * (Sec. 4.1).  The compact field sigma has a flat measure on [-pi, pi), so
+ * the local action S_g of Eq. (5) vanishes and the molecular dynamics (MD)
+ * Hamiltonian of the field and its conjugate momenta pi is
+ *   H(sigma, pi) = 1/2 sum pi^2 + S_p(sigma),   S_p = phi . x,   x = Q^{-1} phi.
+ * Force.  dS_p/dsigma = -x^T (dQ/dsigma) x = -2 (M x)^T (dM/dsigma) x, and
+ * sigma_{n,s} enters M only through the time link A_{n,s+1} (row s+1 of M
+ * reads the field of slice s), so with y = M x
+ *   dS_p/dsigma_{n,s} = -2 y_{n,s'} (dA_{n,s'}/dsigma_{n,s}) x_{n,s},  s' = s+1 mod nt,
+ *   dA_{n,s'}/dsigma_{n,s} = -+ exp(dtau mu) b cos sigma_{n,s}  (+ when s' = 0).
+ * MD: the leapfrog integrator (half step in pi, alternating full steps in
+ * sigma and pi, closing half step in pi); every force evaluation solves
+ * Q x = phi by oracle_cg from x = 0.  Metropolis: the end point is accepted
+ * when u < exp(-(H_end - H_start)), u uniform on [0, 1) supplied by the
+ * caller; otherwise sigma returns to its start.  The pseudofermion heatbath
+ * phi = M^T eta takes eta from the caller (density exp(-eta.eta), i.e.
+ * variance 1/2 per component, so that phi has density exp(-S_p)).
+ */
+
+typedef struct {
+    double h_start;      /* H at the start of the trajectory */
+    double h_end;        /* H at its end */
+    int32_t solves;      /* CG solves (force evaluations) */
+    int32_t cg_iters;    /* CG iterations over all solves */
+    int32_t accepted;    /* Metropolis decision */
+    int32_t failed;      /* a CG solve did not converge */
+} oracle_md_result;
+
+/* F[n + Vs s] = dS_p/dsigma_{n,s} for x = Q^{-1} phi. */
+void oracle_force(const oracle_lattice* L, const double* sigma, const double* x, double* F) {
+    long Vs = spatial_volume(L);
+    long V = oracle_volume(L);
+    double* A = (double*)malloc(sizeof(double) * V);
+    double* y = (double*)malloc(sizeof(double) * V);
+    if (!A || !y) {
+        free(A); free(y);
+        for (long i = 0; i < V; ++i) F[i] = NAN;
+        return;
+    }
+    oracle_links(L, sigma, A);
+    oracle_apply_M(L, A, x, y);
+    double b = oracle_hs_coupling(L->dtau, L->U);
+    double scale = exp(L->dtau * L->mu);
+    for (long s = 0; s < L->nt; ++s) {
+        long sp = (s + 1) % L->nt;
+        double sign = (sp == 0) ? 1.0 : -1.0;
+        for (long n = 0; n < Vs; ++n) {
+            double dA = sign * scale * b * cos(sigma[n + Vs * s]);
+            F[n + Vs * s] = -2.0 * y[n + Vs * sp] * dA * x[n + Vs * s];
+        }
+    }
+    free(A);
+    free(y);
+}
+
+/* Solve Q(sigma) x = phi and return S_p = phi . x; adds the iterations to
+ * *iters; sets *failed when the solve did not converge. */
+static double md_solve(const oracle_lattice* L, const double* sigma, const double* phi,
+                       double* x, double* A, double tol, int32_t max_iter, int32_t* iters,
+                       int32_t* failed) {
+    long V = oracle_volume(L);
+    oracle_cg_result res;
+    oracle_links(L, sigma, A);
+    int rc = oracle_cg(L, A, phi, x, tol, max_iter, &res, NULL, NULL);
+    *iters += res.iters;
+    if (rc != 0) *failed = 1;
+    return oracle_dot(V, phi, x);
+}
+
+/* One MD trajectory of n_steps leapfrog steps of size eps from (sigma, pi),
+ * both updated in place; fills h_start, h_end, solves, cg_iters, failed.
+ * Returns 0, or -1 on allocation failure. */
+int oracle_md(const oracle_lattice* L, double* sigma, double* pi, const double* phi, double eps,
+              int32_t n_steps, double tol, int32_t max_iter, oracle_md_result* res) {
+    long V = oracle_volume(L);
+    double* x = (double*)malloc(sizeof(double) * V);
+    double* A = (double*)malloc(sizeof(double) * V);
+    double* F = (double*)malloc(sizeof(double) * V);
+    if (!x || !A || !F) {
+        free(x); free(A); free(F);
+        return -1;
+    }
+    memset(res, 0, sizeof(*res));
+    double sp = md_solve(L, sigma, phi, x, A, tol, max_iter, &res->cg_iters, &res->failed);
+    res->solves = 1;
+    res->h_start = 0.5 * oracle_dot(V, pi, pi) + sp;
+    oracle_force(L, sigma, x, F);
+    for (long i = 0; i < V; ++i) pi[i] -= 0.5 * eps * F[i];
+    for (int32_t k = 1; k <= n_steps; ++k) {
+        for (long i = 0; i < V; ++i) sigma[i] += eps * pi[i];
+        sp = md_solve(L, sigma, phi, x, A, tol, max_iter, &res->cg_iters, &res->failed);
+        res->solves += 1;
+        oracle_force(L, sigma, x, F);
+        double c = (k == n_steps) ? 0.5 * eps : eps;
+        for (long i = 0; i < V; ++i) pi[i] -= c * F[i];
+    }
+    res->h_end = 0.5 * oracle_dot(V, pi, pi) + sp;
+    free(x);
+    free(A);
+    free(F);
+    return 0;
+}
+
+/* One HMC trajectory: phi = M^T eta at the starting field, the MD
+ * trajectory from (sigma, pi0), then the Metropolis decision with u.
+ * sigma is replaced by the end point when accepted and left unchanged
+ * otherwise; pi0 is not modified.  Returns as oracle_md. */
+int oracle_hmc(const oracle_lattice* L, double* sigma, const double* eta, const double* pi0,
+               double u, double eps, int32_t n_steps, double tol, int32_t max_iter,
+               oracle_md_result* res) {
+    long V = oracle_volume(L);
+    double* A = (double*)malloc(sizeof(double) * V);
+    double* phi = (double*)malloc(sizeof(double) * V);
+    double* s1 = (double*)malloc(sizeof(double) * V);
+    double* p1 = (double*)malloc(sizeof(double) * V);
+    if (!A || !phi || !s1 || !p1) {
+        free(A); free(phi); free(s1); free(p1);
+        return -1;
+    }
+    oracle_links(L, sigma, A);
+    oracle_apply_Mt(L, A, eta, phi);
+    memcpy(s1, sigma, sizeof(double) * V);
+    memcpy(p1, pi0, sizeof(double) * V);
+    int rc = oracle_md(L, s1, p1, phi, eps, n_steps, tol, max_iter, res);
+    if (rc == 0) {
+        res->accepted = (!res->failed && u < exp(-(res->h_end - res->h_start))) ? 1 : 0;
+        if (res->accepted) memcpy(sigma, s1, sizeof(double) * V);
+    }
+    free(A); free(phi); free(s1); free(p1);
+    return rc;
+}
