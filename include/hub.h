@@ -185,6 +185,60 @@ HUB_API hub_status hub_pcg_solve(const hub_lattice* lat, const double* sigma,
                          const hub_cheb_opts* cheb, hub_cg_stats* out,
                          void* stream);
 
+/* ---- Hybrid Monte Carlo, the phi-algorithm (Sec. 4.1) --------------------
+ * (det M)^2 = det Q is represented by a pseudofermion field phi with action
+ * S_p = phi^T Q^{-1} phi (Sec. 4.1).  The compact field sigma has a flat
+ * measure, so the MD Hamiltonian of sigma and its momenta pi is
+ *   H = 1/2 pi.pi + S_p,   S_p = phi . x,   x = Q^{-1} phi,
+ * and the force is (sigma_{n,s} enters M only through A_{n,s+1 mod nt})
+ *   dS_p/dsigma_{n,s} = -2 (M x)_{n,s+1} (dA_{n,s+1}/dsigma_{n,s}) x_{n,s},
+ *   dA_{n,s+1}/dsigma_{n,s} = -+ exp(dtau mu) b cos sigma_{n,s}  (+ on the wrap). */
+
+/* force[i] = dS_p/dsigma_i at every site, for x = Q^{-1} phi (any x is
+ * accepted: the formula is evaluated as written).  sigma, x, force: device
+ * FP64[nx^d * nt]; force distinct from both inputs.  Asynchronous. */
+HUB_API hub_status hub_hmc_force(const hub_lattice* lat, const double* sigma, const double* x,
+                         double* force, void* stream);
+
+typedef struct {
+    int32_t n_steps;  /* leapfrog steps per trajectory, >= 1 */
+    int32_t reserved; /* must be 0 */
+    double eps;       /* MD step size, finite and > 0 */
+    hub_cg_opts cg;   /* solver of every force evaluation (as hub_cg_solve) */
+} hub_md_opts;
+
+typedef struct {
+    double h_start;   /* H at the start of the trajectory */
+    double h_end;     /* H at its end */
+    int32_t solves;   /* CG solves = force evaluations (n_steps + 1) */
+    int32_t cg_iters; /* CG iterations over all solves */
+    int32_t accepted; /* hub_hmc_trajectory: Metropolis decision */
+    int32_t status;   /* hub_status of the call */
+} hub_md_stats;
+
+/* One leapfrog MD trajectory from (sigma, pi), both device FP64[V] updated in
+ * place: pi -= eps/2 F; then n_steps times { sigma += eps pi; solve
+ * Q x = phi; pi -= eps F } with the last kick halved.  Every force
+ * evaluation solves Q x = phi from x = 0 with opts->cg (the same solver as
+ * hub_cg_solve).  phi: device FP64[V].  Blocks until done.  HUB_E_NOCONV if
+ * a solve fails: the trajectory stops there, sigma and pi hold the point
+ * reached. */
+HUB_API hub_status hub_md_trajectory(const hub_lattice* lat, double* sigma, double* pi,
+                             const double* phi, const hub_md_opts* opts,
+                             hub_md_stats* out, void* stream);
+
+/* One HMC trajectory: the pseudofermion heatbath phi = M^T eta at the
+ * starting field, the MD trajectory of hub_md_trajectory from (sigma, pi0)
+ * on copies, and the Metropolis step: the end point replaces sigma when
+ * u < exp(-(H_end - H_start)); otherwise sigma is left untouched.  The
+ * random numbers come from the caller: eta (device FP64[V], density
+ * exp(-eta.eta), i.e. variance 1/2 per component), pi0 (device FP64[V],
+ * standard normal; not modified), u (uniform on [0, 1)).  Blocks until done;
+ * a failed solve returns HUB_E_NOCONV with sigma untouched. */
+HUB_API hub_status hub_hmc_trajectory(const hub_lattice* lat, double* sigma, const double* eta,
+                              const double* pi0, double u, const hub_md_opts* opts,
+                              hub_md_stats* out, void* stream);
+
 /* ---- Serving: continuous batching of CG solves from many HMC chains ----
  * A server owns one worker thread, one HIP stream and the resident state of
  * every chain it has seen (field, links, Krylov vectors).  Requests are

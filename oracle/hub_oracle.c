@@ -122,7 +122,7 @@ void oracle_apply_M(const oracle_lattice* L, const double* A, const double* x,
                     double* y) {
     long Vs = spatial_volume(L);
     double kappa = L->dtau * L->t_hop;
-#pragma omp parallel for schedule(static)
+#pragma omp parallel for schedule(static) if (Vs * L->nt >= 65536)
     for (long s = 0; s < L->nt; ++s) {
         long sm = (s - 1 + L->nt) % L->nt;
         for (long n = 0; n < Vs; ++n) {
@@ -142,7 +142,7 @@ void oracle_apply_Mt(const oracle_lattice* L, const double* A, const double* y,
                      double* z) {
     long Vs = spatial_volume(L);
     double kappa = L->dtau * L->t_hop;
-#pragma omp parallel for schedule(static)
+#pragma omp parallel for schedule(static) if (Vs * L->nt >= 65536)
     for (long s = 0; s < L->nt; ++s) {
         long sp = (s + 1) % L->nt;
         for (long n = 0; n < Vs; ++n) {

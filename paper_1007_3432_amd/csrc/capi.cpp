@@ -1,6 +1,7 @@
 // Exported C ABI of libhub (declarations and contracts in include/hub.h).
 #include <cmath>
 #include <cstdint>
+#include <initializer_list>
 #include <new>
 
 #include "cheb.h"
@@ -79,6 +80,32 @@ hub_status check_cg_args(const hub_lattice* lat, const double* sigma, const doub
     if ((const void*)x == (const void*)phi || (const void*)x == (const void*)sigma)
         return set_error(HUB_E_INVALID, "x aliases an input");
     return HUB_OK;
+}
+
+hub_status check_md_opts(const hub_md_opts* o) {
+    if (!o) return set_error(HUB_E_INVALID, "md opts is NULL");
+    if (o->n_steps < 1) return set_error(HUB_E_INVALID, "n_steps = %d, expected >= 1", o->n_steps);
+    if (o->reserved != 0) return set_error(HUB_E_INVALID, "md opts reserved must be 0");
+    if (!std::isfinite(o->eps) || !(o->eps > 0))
+        return set_error(HUB_E_INVALID, "eps = %g, expected finite > 0", o->eps);
+    const hub_cg_opts c = o->cg;
+    if (!valid_dtype(c.bulk) || !valid_dtype(c.link) || c.bulk == HUB_F16 ||
+        !valid_pair(c.bulk, c.link))
+        return set_error(HUB_E_INVALID, "md opts: bad solver precision (bulk %d, link %d)",
+                         (int)c.bulk, (int)c.link);
+    if (!(c.tol > 0) || !(c.tol < 1))
+        return set_error(HUB_E_INVALID, "md opts: tol = %g, expected 0 < tol < 1", c.tol);
+    if (c.max_iter < 1) return set_error(HUB_E_INVALID, "md opts: max_iter must be >= 1");
+    if (c.bulk == HUB_F32 && c.reliable_every < 1)
+        return set_error(HUB_E_INVALID, "md opts: reliable_every must be >= 1");
+    return HUB_OK;
+}
+
+bool distinct(std::initializer_list<const void*> ps) {
+    for (auto a = ps.begin(); a != ps.end(); ++a)
+        for (auto b = a + 1; b != ps.end(); ++b)
+            if (*a == *b) return false;
+    return true;
 }
 
 hub_status check_cheb(const hub_cheb_opts* c) {
@@ -184,6 +211,55 @@ hub_status hub_pcg_solve(const hub_lattice* lat, const double* sigma, const doub
     if (opts->bulk != HUB_F64 || opts->link != HUB_F64)
         return set_error(HUB_E_INVALID, "hub_pcg_solve runs in FP64: bulk and link must be F64");
     return pcg_solve(g, sigma, phi, x, *opts, *cheb, out, (hipStream_t)stream);
+    HUB_GUARD_END
+}
+
+hub_status hub_hmc_force(const hub_lattice* lat, const double* sigma, const double* x,
+                         double* force, void* stream) {
+    HUB_GUARD_BEGIN
+    clear_error();
+    Geom g;
+    HUB_TRY(make_geom(lat, &g));
+    HUB_TRY(check_vec_ptr(sigma, "sigma"));
+    HUB_TRY(check_vec_ptr(x, "x"));
+    HUB_TRY(check_vec_ptr(force, "force"));
+    if (!distinct({sigma, x, force})) return set_error(HUB_E_INVALID, "force aliases an input");
+    return hmc_force(g, sigma, x, force, (hipStream_t)stream);
+    HUB_GUARD_END
+}
+
+hub_status hub_md_trajectory(const hub_lattice* lat, double* sigma, double* pi,
+                             const double* phi, const hub_md_opts* opts, hub_md_stats* out,
+                             void* stream) {
+    HUB_GUARD_BEGIN
+    clear_error();
+    Geom g;
+    HUB_TRY(make_geom(lat, &g));
+    HUB_TRY(check_md_opts(opts));
+    HUB_TRY(check_vec_ptr(sigma, "sigma"));
+    HUB_TRY(check_vec_ptr(pi, "pi"));
+    HUB_TRY(check_vec_ptr(phi, "phi"));
+    if (!distinct({sigma, pi, phi})) return set_error(HUB_E_INVALID, "sigma, pi and phi alias");
+    return md_trajectory(g, sigma, pi, phi, nullptr, nullptr, 0.0, *opts, out,
+                         (hipStream_t)stream);
+    HUB_GUARD_END
+}
+
+hub_status hub_hmc_trajectory(const hub_lattice* lat, double* sigma, const double* eta,
+                              const double* pi0, double u, const hub_md_opts* opts,
+                              hub_md_stats* out, void* stream) {
+    HUB_GUARD_BEGIN
+    clear_error();
+    Geom g;
+    HUB_TRY(make_geom(lat, &g));
+    HUB_TRY(check_md_opts(opts));
+    HUB_TRY(check_vec_ptr(sigma, "sigma"));
+    HUB_TRY(check_vec_ptr(eta, "eta"));
+    HUB_TRY(check_vec_ptr(pi0, "pi0"));
+    if (!distinct({sigma, eta, pi0})) return set_error(HUB_E_INVALID, "sigma, eta and pi0 alias");
+    if (!std::isfinite(u)) return set_error(HUB_E_INVALID, "u is not finite");
+    return md_trajectory(g, sigma, nullptr, nullptr, eta, pi0, u, *opts, out,
+                         (hipStream_t)stream);
     HUB_GUARD_END
 }
 

@@ -50,4 +50,11 @@ hub_status cg_solve(const Geom& g, const double* sigma, const double* phi,
                     double* x, const hub_cg_opts& o, hub_cg_stats* out,
                     hipStream_t st);
 
+// HMC (hmc.hip; arguments already validated).
+hub_status hmc_force(const Geom& g, const double* sigma, const double* x, double* F,
+                     hipStream_t st);
+hub_status md_trajectory(const Geom& g, double* sigma, double* pi, const double* phi,
+                         const double* eta, const double* pi0, double u, const hub_md_opts& o,
+                         hub_md_stats* out, hipStream_t st);
+
 }  // namespace hub

@@ -56,6 +56,23 @@ class CGStats(ctypes.Structure):
                 "status": STATUS_NAMES.get(self.status, str(self.status))}
 
 
+class MDOpts(ctypes.Structure):
+    _fields_ = [("n_steps", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("eps", ctypes.c_double), ("cg", CGOpts)]
+
+
+class MDStats(ctypes.Structure):
+    _fields_ = [("h_start", ctypes.c_double), ("h_end", ctypes.c_double),
+                ("solves", ctypes.c_int32), ("cg_iters", ctypes.c_int32),
+                ("accepted", ctypes.c_int32), ("status", ctypes.c_int32)]
+
+    def as_dict(self) -> dict:
+        return {"h_start": self.h_start, "h_end": self.h_end,
+                "delta_h": self.h_end - self.h_start, "solves": self.solves,
+                "cg_iters": self.cg_iters, "accepted": bool(self.accepted),
+                "status": STATUS_NAMES.get(self.status, str(self.status))}
+
+
 class ServeOpts(ctypes.Structure):
     _fields_ = [("hbm_budget_bytes", ctypes.c_size_t), ("max_inflight", ctypes.c_int32),
                 ("engine", ctypes.c_int32), ("cg", CGOpts)]
@@ -77,6 +94,10 @@ def cg_opts(bulk: int = F64, link: int | None = None, tol: float = 1e-10,
     if link is None:
         link = F64 if bulk == F64 else F32
     return CGOpts(bulk, link, tol, max_iter, reliable_every)
+
+
+def md_opts(n_steps: int, eps: float, cg: CGOpts | None = None) -> MDOpts:
+    return MDOpts(int(n_steps), 0, float(eps), cg if cg is not None else cg_opts())
 
 
 def cheb_opts(n: int, eps: float, scale: float = 0.0) -> ChebOpts:
@@ -111,6 +132,11 @@ def load():
     lib.hub_apply_cheb_noalloc.argtypes = [lp, vp, vp, vp, ctypes.POINTER(ChebOpts), vp]
     lib.hub_pcg_solve.argtypes = [lp, vp, vp, vp, ctypes.POINTER(CGOpts),
                                   ctypes.POINTER(ChebOpts), ctypes.POINTER(CGStats), vp]
+    lib.hub_hmc_force.argtypes = [lp, vp, vp, vp, vp]
+    lib.hub_md_trajectory.argtypes = [lp, vp, vp, vp, ctypes.POINTER(MDOpts),
+                                      ctypes.POINTER(MDStats), vp]
+    lib.hub_hmc_trajectory.argtypes = [lp, vp, vp, vp, ctypes.c_double, ctypes.POINTER(MDOpts),
+                                       ctypes.POINTER(MDStats), vp]
     lib.hub_serve_create.argtypes = [ctypes.POINTER(ServeOpts), ctypes.POINTER(vp)]
     lib.hub_serve_submit.argtypes = [vp, ctypes.c_int32, lp, vp, vp,
                                      ctypes.POINTER(ctypes.c_uint64)]
@@ -118,6 +144,7 @@ def load():
     lib.hub_serve_destroy.argtypes = [vp]
     for f in (lib.hub_links_from_sigma, lib.hub_apply_M, lib.hub_apply_MtM, lib.hub_cg_solve,
               lib.hub_apply_cheb, lib.hub_apply_cheb_noalloc, lib.hub_pcg_solve,
+              lib.hub_hmc_force, lib.hub_md_trajectory, lib.hub_hmc_trajectory,
               lib.hub_serve_create, lib.hub_serve_submit, lib.hub_serve_poll,
               lib.hub_serve_destroy):
         f.restype = ctypes.c_int
@@ -222,6 +249,38 @@ def hub_pcg_solve(lat: Lattice, sigma, phi, x, opts: CGOpts, cheb: ChebOpts, str
                                   _stream(stream))
     ok = (HUB_OK,) if raise_on_noconv else (HUB_OK, HUB_E_NOCONV)
     _check(status, "hub_pcg_solve", ok)
+    return st.as_dict()
+
+
+def hub_hmc_force(lat: Lattice, sigma, x, force, stream=None) -> None:
+    V = lat.volume
+    _check(load().hub_hmc_force(ctypes.byref(lat), _dev_ptr(sigma, F64, V, "sigma"),
+                                _dev_ptr(x, F64, V, "x"), _dev_ptr(force, F64, V, "force"),
+                                _stream(stream)), "hub_hmc_force")
+
+
+def hub_md_trajectory(lat: Lattice, sigma, pi, phi, opts: MDOpts, stream=None,
+                      raise_on_noconv: bool = True) -> dict:
+    V = lat.volume
+    st = MDStats()
+    status = load().hub_md_trajectory(ctypes.byref(lat), _dev_ptr(sigma, F64, V, "sigma"),
+                                      _dev_ptr(pi, F64, V, "pi"), _dev_ptr(phi, F64, V, "phi"),
+                                      ctypes.byref(opts), ctypes.byref(st), _stream(stream))
+    ok = (HUB_OK,) if raise_on_noconv else (HUB_OK, HUB_E_NOCONV)
+    _check(status, "hub_md_trajectory", ok)
+    return st.as_dict()
+
+
+def hub_hmc_trajectory(lat: Lattice, sigma, eta, pi0, u: float, opts: MDOpts, stream=None,
+                       raise_on_noconv: bool = True) -> dict:
+    V = lat.volume
+    st = MDStats()
+    status = load().hub_hmc_trajectory(ctypes.byref(lat), _dev_ptr(sigma, F64, V, "sigma"),
+                                       _dev_ptr(eta, F64, V, "eta"),
+                                       _dev_ptr(pi0, F64, V, "pi0"), float(u),
+                                       ctypes.byref(opts), ctypes.byref(st), _stream(stream))
+    ok = (HUB_OK,) if raise_on_noconv else (HUB_OK, HUB_E_NOCONV)
+    _check(status, "hub_hmc_trajectory", ok)
     return st.as_dict()
 
 

@@ -18,7 +18,8 @@ def lib():
 def test_header_declares_the_api():
     names = set(hub.declared_symbols())
     assert {"hub_links_from_sigma", "hub_apply_M", "hub_apply_MtM", "hub_cg_solve",
-            "hub_apply_cheb", "hub_apply_cheb_noalloc", "hub_pcg_solve", "hub_serve_create", "hub_serve_submit", "hub_serve_poll",
+            "hub_apply_cheb", "hub_apply_cheb_noalloc", "hub_pcg_solve",
+            "hub_hmc_force", "hub_md_trajectory", "hub_hmc_trajectory", "hub_serve_create", "hub_serve_submit", "hub_serve_poll",
             "hub_serve_destroy", "hub_last_error"} <= names
 
 
@@ -105,6 +106,39 @@ def test_cheb_noalloc_rejects_oversize_before_launch(lib):
                                        ctypes.byref(hub.cheb_opts(4, 0.01)), None)
         assert s == hub.HUB_E_NOMEM
         assert "64 MiB" in hub.last_error() or "workspace" in hub.last_error()
+
+
+@pytest.mark.parametrize("opts", [hub.MDOpts(0, 0, 0.1, hub.cg_opts()),
+                                  hub.MDOpts(4, 1, 0.1, hub.cg_opts()),
+                                  hub.MDOpts(4, 0, 0.0, hub.cg_opts()),
+                                  hub.MDOpts(4, 0, math.nan, hub.cg_opts()),
+                                  hub.MDOpts(4, 0, 0.1, hub.cg_opts(tol=0.0)),
+                                  hub.MDOpts(4, 0, 0.1, hub.CGOpts(hub.F16, hub.F16, 1e-10, 9, 50))])
+def test_md_options_validated(lib, opts):
+    lat = hub.lattice(1, 8, 8)
+    st = hub.MDStats()
+    assert lib.hub_md_trajectory(ctypes.byref(lat), ctypes.c_void_p(16), ctypes.c_void_p(32),
+                                 ctypes.c_void_p(48), ctypes.byref(opts), ctypes.byref(st),
+                                 None) == hub.HUB_E_INVALID
+    assert lib.hub_hmc_trajectory(ctypes.byref(lat), ctypes.c_void_p(16), ctypes.c_void_p(32),
+                                  ctypes.c_void_p(48), ctypes.c_double(0.5), ctypes.byref(opts),
+                                  ctypes.byref(st), None) == hub.HUB_E_INVALID
+
+
+def test_hmc_pointer_checks(lib):
+    lat = hub.lattice(1, 8, 8)
+    st = hub.MDStats()
+    good = hub.md_opts(2, 0.1)
+    assert lib.hub_hmc_force(ctypes.byref(lat), ctypes.c_void_p(16), ctypes.c_void_p(32),
+                             ctypes.c_void_p(16), None) == hub.HUB_E_INVALID
+    assert lib.hub_hmc_force(ctypes.byref(lat), ctypes.c_void_p(16), ctypes.c_void_p(40),
+                             ctypes.c_void_p(64), None) == hub.HUB_E_INVALID
+    assert lib.hub_md_trajectory(ctypes.byref(lat), ctypes.c_void_p(16), ctypes.c_void_p(16),
+                                 ctypes.c_void_p(48), ctypes.byref(good), ctypes.byref(st),
+                                 None) == hub.HUB_E_INVALID
+    assert lib.hub_hmc_trajectory(ctypes.byref(lat), ctypes.c_void_p(16), ctypes.c_void_p(32),
+                                  ctypes.c_void_p(48), ctypes.c_double(math.inf),
+                                  ctypes.byref(good), ctypes.byref(st), None) == hub.HUB_E_INVALID
 
 
 def test_pcg_requires_fp64(lib):
