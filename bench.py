@@ -77,8 +77,10 @@ def _args():
     ap.add_argument("--no-serve", action="store_true", help="skip the serving workload")
     ap.add_argument("--legs", default="all",
                     help="comma-separated legs beside the headline: sweeps, c0, c2, c3, "
-                         "pcg, serve, cgprof (a few CG iterations per solver, for counter "
-                         "runs); 'all' = every leg but cgprof, 'none' = headline only")
+                         "pcg, hmc, serve, cgprof (a few CG iterations per solver, for "
+                         "counter runs), mv (the paper's MV experiment: fused vs naive vs "
+                         "CPU over lattice sizes, about a minute of host time); 'all' = "
+                         "every leg but cgprof and mv, 'none' = headline only")
     ap.add_argument("--cgprof-iters", type=int, default=60,
                     help="iterations per solve of the cgprof leg")
     ap.add_argument("--no-oracle", action="store_true",
@@ -365,6 +367,182 @@ def cg_profile_leg(hub, iters: int):
     return out
 
 
+def force_rate(hub, shape, calls: int = 50):
+    """hub_hmc_force alone (sigma 8 + x 8 in, F 8 out per site): HIP events
+    around a graph replay of `calls` launches."""
+    import torch
+    from paper_1007_3432_amd import inputs
+    d, nx, nt = shape
+    lat = hub.lattice(d, nx, nt)
+    V = lat.volume
+    sigma, _ = inputs.sigma_eta(d, nx, nt, seed=0)
+    sig_d, x_d = _dev(sigma), _dev(inputs.random_vector(V, 5))
+    F = torch.empty_like(x_d)
+    hub.hub_hmc_force(lat, sig_d, x_d, F)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        for _ in range(calls):
+            hub.hub_hmc_force(lat, sig_d, x_d, F)
+    g.replay()
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    g.replay()
+    e1.record()
+    torch.cuda.synchronize()
+    us = e0.elapsed_time(e1) * 1e3 / calls
+    return {"shape": list(shape), "avg_launch_us": us, "bytes_per_site": 24,
+            "achieved_gbs": 24 * V / us / 1e3, "frac": 24 * V / us / 1e3 / HBM_PEAK_GBS}
+
+
+def hmc_leg(hub, check: bool = True, n_traj: int = 20):
+    """HMC trajectories (Sec. 4.1): a chain of n_traj trajectories on the
+    d=1 32 x 64 lattice (10 leapfrog steps of 0.05, FP64 CG to 1e-10 per
+    force), the first one also run by the oracle on the same random numbers;
+    one trajectory on d=3 16^3 x 160 with mixed-precision solves; and the
+    force kernel's rate at 1M and 8.4M sites."""
+    import math
+    import numpy as np
+    import torch
+    from paper_1007_3432_amd import inputs
+    out = {}
+    shape = (1, 32, 64)
+    lat = hub.lattice(*shape)
+    V = lat.volume
+    sigma0, _ = inputs.sigma_eta(*shape, seed=0)
+    sig_d = _dev(sigma0)
+    rng = np.random.default_rng(2024)
+    opts = hub.md_opts(10, 0.05, hub.cg_opts(hub.F64))
+    recs, first = [], None
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(n_traj):
+        eta = rng.standard_normal(V) / math.sqrt(2.0)
+        pi0 = rng.standard_normal(V)
+        u = float(rng.uniform())
+        if k == 0:
+            first = (sig_d.cpu().numpy(), eta, pi0, u)
+        st = hub.hub_hmc_trajectory(lat, sig_d, _dev(eta), _dev(pi0), u, opts)
+        recs.append(st)
+        if k == 0:
+            first = first + (sig_d.cpu().numpy(), st)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    out["c0_d1_32x64"] = {
+        "trajectories": n_traj, "n_steps": 10, "eps": 0.05, "solver": "fp64",
+        "trajectories_per_s": n_traj / dt, "ms_per_trajectory": dt / n_traj * 1e3,
+        "acceptance": float(np.mean([r["accepted"] for r in recs])),
+        "mean_abs_delta_h": float(np.mean([abs(r["delta_h"]) for r in recs])),
+        "solves_per_trajectory": recs[0]["solves"],
+        "mean_cg_iters_per_solve": float(np.mean([r["cg_iters"] / r["solves"] for r in recs]))}
+    if check:
+        import oracle
+        s_in, eta, pi0, u, s_out, st = first
+        olat = oracle.Lattice(*shape)
+        s_ref, r_ref = oracle.hmc(olat, s_in, eta, pi0, u, 0.05, 10)
+        out["c0_d1_32x64"]["oracle_check_first_trajectory"] = {
+            "delta_h_gpu": st["delta_h"], "delta_h_oracle": r_ref.delta_h,
+            "accepted_gpu": st["accepted"], "accepted_oracle": r_ref.accepted,
+            "max_abs_sigma_diff": float(np.max(np.abs(s_out - s_ref)))}
+    shape = (3, 16, 160)
+    lat = hub.lattice(*shape)
+    V = lat.volume
+    sigma, _ = inputs.sigma_eta(*shape, seed=0)
+    rng = np.random.default_rng(2025)
+    eta = rng.standard_normal(V) / math.sqrt(2.0)
+    pi0 = rng.standard_normal(V)
+    sig_d = _dev(sigma)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    st = hub.hub_hmc_trajectory(lat, sig_d, _dev(eta), _dev(pi0), 0.5,
+                                hub.md_opts(4, 0.01, hub.cg_opts(hub.F32, hub.F32)))
+    torch.cuda.synchronize()
+    out["c2_d3_16x160"] = dict(st, n_steps=4, eps=0.01, solver="mixed f32",
+                               ms=(time.perf_counter() - t0) * 1e3)
+    out["force_c1_d1_2048x512"] = force_rate(hub, (1, 2048, 512))
+    out["force_c3_d3_32x256"] = force_rate(hub, (3, 32, 256), 20)
+    return out
+
+
+def mv_table(hub, cpu: bool = True):
+    """The paper's matrix-vector experiment (Sec. 4.3, Fig. 3) on this GPU:
+    Q x = M^T M x on d=3 lattices Nx in {8, 16, 32, 64} x Nt in {32, 64,
+    128, 256} (and d=1 for the 30-350x context), FP64.  Per lattice: the
+    fused sweep (hub_apply_MtM), the naive one-lane-per-site M then M^T
+    (two hub_apply_M calls, the design the paper starts from), and the
+    oracle's M^T M on one host thread (the paper's CPU methodology) and on
+    all host cores.  GPU calls: repeated on one buffer set, captured in a
+    HIP graph, HIP events around a replay."""
+    import numpy as np
+    import torch
+    from paper_1007_3432_amd import inputs
+    if cpu:
+        import oracle
+    rows = []
+    grid = [(3, nx, nt) for nx in (8, 16, 32, 64) for nt in (32, 64, 128, 256)]
+    grid += [(1, nx, nt) for nx in (256, 1024, 4096) for nt in (64, 256, 1024)]
+    for d, nx, nt in grid:
+        lat = hub.lattice(d, nx, nt)
+        V = lat.volume
+        rng = np.random.default_rng(7)
+        sigma = rng.uniform(-np.pi, np.pi, V)
+        x_h = rng.standard_normal(V)
+        sig_d, x_d = _dev(sigma), _dev(x_h)
+        A_d = torch.empty_like(x_d)
+        hub.hub_links_from_sigma(lat, sig_d, A_d, hub.F64)
+        del sig_d
+        y_d, z_d = torch.empty_like(x_d), torch.empty_like(x_d)
+        calls = int(min(2000, max(10, 2e9 / (24 * V))))
+
+        def timed(body):
+            body()
+            torch.cuda.synchronize()
+            g = torch.cuda.CUDAGraph()
+            with torch.cuda.graph(g):
+                for _ in range(calls):
+                    body()
+            g.replay()
+            torch.cuda.synchronize()
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record()
+            g.replay()
+            e1.record()
+            torch.cuda.synchronize()
+            del g
+            return e0.elapsed_time(e1) * 1e3 / calls
+
+        fused = timed(lambda: hub.hub_apply_MtM(lat, A_d, hub.F64, hub.F64, x_d, z_d))
+        naive = timed(lambda: (hub.hub_apply_M(lat, A_d, hub.F64, hub.F64, x_d, y_d, 0),
+                               hub.hub_apply_M(lat, A_d, hub.F64, hub.F64, y_d, z_d, 1)))
+        row = {"d": d, "nx": nx, "nt": nt, "sites": V, "gpu_calls": calls,
+               "fused_us": fused, "fused_gbs": 24 * V / fused / 1e3,
+               "naive_two_pass_us": naive, "naive_gbs_at_24B": 24 * V / naive / 1e3,
+               "fused_vs_naive": naive / fused}
+        del x_d, y_d, z_d, A_d
+        if cpu:
+            olat = oracle.Lattice(d, nx, nt)
+            A = oracle.links(olat, sigma)
+            for label, threads in (("cpu_1thread_ms", 1), ("cpu_all_cores_ms",
+                                                          os.cpu_count() or 1)):
+                oracle.set_threads(threads)
+                n, t0 = 0, time.perf_counter()
+                while n == 0 or (time.perf_counter() - t0 < 0.3 and n < 50):
+                    oracle.apply_MtM(olat, A, x_h)
+                    n += 1
+                row[label] = (time.perf_counter() - t0) / n * 1e3
+            row["speedup_fused_vs_cpu_1thread"] = row["cpu_1thread_ms"] * 1e3 / fused
+            row["speedup_naive_vs_cpu_1thread"] = row["cpu_1thread_ms"] * 1e3 / naive
+            row["speedup_fused_vs_cpu_all_cores"] = row["cpu_all_cores_ms"] * 1e3 / fused
+        rows.append(row)
+        _progress("mv d=%d %dx%d: fused %.1f us, naive %.1f us" % (d, nx, nt, fused, naive))
+        torch.cuda.empty_cache()
+    return {"rows": rows, "cpu_model": cpu_model(), "nproc": os.cpu_count(),
+            "note": "oracle parallel loops switch on at >= 65536 sites; smaller lattices "
+                    "run on one thread in both CPU columns"}
+
+
 def launch_floor_us(reps: int = 1000) -> float:
     """Back-to-back graph-replayed launches of a one-element kernel."""
     import torch
@@ -569,14 +747,14 @@ def main():
     hub.load()
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     check = not a.no_oracle
-    all_legs = {"sweeps", "c0", "c2", "c3", "pcg", "serve"}
+    all_legs = {"sweeps", "c0", "c2", "c3", "pcg", "hmc", "serve"}
     if a.no_detail or a.legs == "none":
         legs = set()
     elif a.legs == "all":
         legs = set(all_legs)
     else:
         legs = set(a.legs.split(","))
-        unknown = legs - all_legs - {"cgprof"}
+        unknown = legs - all_legs - {"cgprof", "mv"}
         if unknown:
             raise SystemExit(f"unknown legs: {sorted(unknown)}")
     if a.no_serve:
@@ -745,6 +923,12 @@ def main():
         grid = [(n, e) for n in (4, 8, 16, 32) for e in (1e-4, 4e-4, 1.6e-3)]
         detail["pcg_c1_d1_2048x512"] = pcg_compare(hub, (1, 2048, 512), grid)
         detail["pcg_c2_d3_16x160"] = pcg_compare(hub, (3, 16, 160), grid)
+    if "hmc" in legs:
+        _progress("HMC trajectories")
+        detail["hmc"] = hmc_leg(hub, check=check)
+    if "mv" in legs:
+        _progress("MV experiment table")
+        detail["mv_table"] = mv_table(hub, cpu=not a.no_cpu)
     if "serve" in legs:
         _progress("serving: Poisson 200/s")
         detail["serve_poisson_200_per_s"] = serve_bench(hub, a.engine, a.serve_seconds,
