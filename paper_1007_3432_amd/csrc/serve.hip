@@ -67,12 +67,22 @@ struct EpochCtl {
     int32_t pad;
 };
 
-// LDS of the largest tile the serving kernel runs (FP64 residual sweeps).
+// LDS elements a serving tile needs (d = 1 tiles use none).
+static int serve_lds_elems(int kind, int variant) {
+    if (kind != kSweepD3) return 0;
+    switch (variant) {
+        case kD3_8x8x8: return d3_lds_elems<8, 8, 8>();
+        case kD3_16x4x4: return d3_lds_elems<16, 4, 4>();
+        default: return d3_lds_elems<32, 8, 4>();
+    }
+}
+
+// LDS of the largest tile the serving kernel runs (FP64 residual sweeps):
+// what the persistent engine reserves, as its one launch runs every phase.
 constexpr int kServeLdsBytes = [] {
     int m = d1_lds_elems<256, 4>();
     m = std::max(m, d3_lds_elems<8, 8, 8>());
     m = std::max(m, d3_lds_elems<16, 4, 4>());
-    m = std::max(m, d1_lds_elems<256, 4>());
     m = std::max(m, d3_lds_elems<32, 8, 4>());
     return m * 8;
 }();
@@ -162,38 +172,49 @@ struct Sums2 {
     double a, b;
 };
 
-// One sweep tile of solve *S, as its own function: each (op, tile shape)
-// pair is register-allocated on its own, so the kernel needs the largest of
-// them rather than the sum of everything inlined into one body.  Returns the
-// block sums (thread 0).
+// One sweep tile of solve *S.  Returns the block sums (thread 0).  The
+// batched engine launches one kernel per tile shape, with these bodies
+// inlined; the persistent engine runs every shape in one kernel and calls
+// them as functions (serve_tile_A / serve_tile_R), each (op, tile shape)
+// pair register-allocated on its own.
 template <class Lnk, int KIND, int A, int B, int C>
-__device__ __noinline__ Sums2 serve_tile_A(const SlotDesc* S, int tile) {
+__device__ __forceinline__ Sums2 serve_tile_A_body(const SlotDesc* S, int tile) {
     const auto op = slot_phaseA<Lnk>(*S);
     double part[1] = {0.0};
     float* lds = reinterpret_cast<float*>(serve_smem);
     if constexpr (KIND == kSweepD1)
         tile_mtm_d1<decltype(op), A, B>(S->g, op, S->tiles_x, tile, lds, part);
     else
-        tile_mtm_d3<decltype(op), A, B, C>(S->g, op, S->tiles_y, S->tiles_z, S->tc, tile, lds,
-                                           part);
+        tile_mtm_d3<decltype(op), A, B, C, 256>(S->g, op, S->tiles_y, S->tiles_z, S->tc, tile,
+                                                lds, part);
     Sums2 r{block_sum<256>(part[0]), 0.0};
     return r;
 }
 
 template <int KIND, int A, int B, int C>
-__device__ __noinline__ Sums2 serve_tile_R(const SlotDesc* S, int tile) {
+__device__ __forceinline__ Sums2 serve_tile_R_body(const SlotDesc* S, int tile) {
     const auto op = slot_residual(*S);
     double part[2] = {0.0, 0.0};
     double* lds = reinterpret_cast<double*>(serve_smem);
     if constexpr (KIND == kSweepD1)
         tile_mtm_d1<decltype(op), A, B>(S->g, op, S->tiles_x, tile, lds, part);
     else
-        tile_mtm_d3<decltype(op), A, B, C>(S->g, op, S->tiles_y, S->tiles_z, S->tc, tile, lds,
-                                           part);
+        tile_mtm_d3<decltype(op), A, B, C, 256>(S->g, op, S->tiles_y, S->tiles_z, S->tc, tile,
+                                                lds, part);
     Sums2 r;
     r.a = block_sum<256>(part[0]);
     r.b = block_sum<256>(part[1]);
     return r;
+}
+
+template <class Lnk, int KIND, int A, int B, int C>
+__device__ __noinline__ Sums2 serve_tile_A(const SlotDesc* S, int tile) {
+    return serve_tile_A_body<Lnk, KIND, A, B, C>(S, tile);
+}
+
+template <int KIND, int A, int B, int C>
+__device__ __noinline__ Sums2 serve_tile_R(const SlotDesc* S, int tile) {
+    return serve_tile_R_body<KIND, A, B, C>(S, tile);
 }
 
 template <class Lnk>
@@ -314,13 +335,15 @@ __global__ __launch_bounds__(256) void k_serve_epoch(const SlotDesc* __restrict_
 // all in-flight solves, with one-block-per-solve finalize launches in place
 // of grid barriers (kernel boundaries are the cheaper device-wide sync).
 
-template <class Lnk>
+// Sweep kernels of one tile shape over the in-flight solves of that shape
+// (slots[0 .. n), whose off_sweep count within the group).
+template <class Lnk, int KIND, int A, int B, int C>
 __global__ __launch_bounds__(256) void k_serve_A(const SlotDesc* __restrict__ slots, int n) {
     const int w = xcd_remap(blockIdx.x, gridDim.x);
     const SlotDesc& S = slots[find_slot(slots, n, w, true)];
     if (S.sc->done != kRunning) return;
     const int tile = w - S.off_sweep;
-    store_deposit<1>(serve_sweep_A<Lnk>(&S, tile), S.partials, tile);
+    store_deposit<1>(serve_tile_A_body<Lnk, KIND, A, B, C>(&S, tile), S.partials, tile);
 }
 
 template <class Lnk>
@@ -358,12 +381,42 @@ __global__ __launch_bounds__(256) void k_serve_fold(const SlotDesc* __restrict__
                      w - S.off_elem);
 }
 
+template <int KIND, int A, int B, int C>
 __global__ __launch_bounds__(256) void k_serve_R(const SlotDesc* __restrict__ slots, int n) {
     const int w = xcd_remap(blockIdx.x, gridDim.x);
     const SlotDesc& S = slots[find_slot(slots, n, w, true)];
     if (!mode_runs(kModeReliable, S.sc->done)) return;
     const int tile = w - S.off_sweep;
-    store_deposit<2>(serve_sweep_R(&S, tile), S.partials, tile);
+    store_deposit<2>(serve_tile_R_body<KIND, A, B, C>(&S, tile), S.partials, tile);
+}
+
+// Launch the phase-A (R = false) or residual (R = true) sweep of one group of
+// solves that share a tile shape.
+template <class Lnk>
+static hipError_t launch_serve_sweep(bool R, int kind, int variant, const SlotDesc* slots, int n,
+                                     int tiles, size_t lds, hipStream_t st) {
+#define HUB_SERVE_CASE(KIND, A, B, C)                                                    \
+    do {                                                                                 \
+        if (R)                                                                           \
+            k_serve_R<KIND, A, B, C><<<tiles, 256, lds, st>>>(slots, n);                  \
+        else                                                                             \
+            k_serve_A<Lnk, KIND, A, B, C><<<tiles, 256, lds, st>>>(slots, n);             \
+    } while (0)
+    if (kind == kSweepD1) {
+        switch (variant) {
+            case kD1_256x4: HUB_SERVE_CASE(kSweepD1, 256, 4, 0); break;
+            case kD1_128x4: HUB_SERVE_CASE(kSweepD1, 128, 4, 0); break;
+            default: HUB_SERVE_CASE(kSweepD1, 64, 4, 0); break;
+        }
+    } else {
+        switch (variant) {
+            case kD3_8x8x8: HUB_SERVE_CASE(kSweepD3, 8, 8, 8); break;
+            case kD3_16x4x4: HUB_SERVE_CASE(kSweepD3, 16, 4, 4); break;
+            default: HUB_SERVE_CASE(kSweepD3, 32, 8, 4); break;
+        }
+    }
+#undef HUB_SERVE_CASE
+    return hipGetLastError();
 }
 
 __global__ __launch_bounds__(256) void k_serve_finR(const SlotDesc* __restrict__ slots) {
@@ -662,12 +715,25 @@ hub_status finish_slot(hub_server* S, int k) {
 }
 
 hub_status run_epoch(hub_server* S) {
-    int n = 0, tot_sweep = 0, tot_elem = 0;
+    // In-flight solves, grouped by tile shape so that each sweep launch runs
+    // one shape: off_sweep counts within the group, off_elem over all.
     std::vector<int> ks;
-    for (int k = 0; k < (int)S->slots.size(); ++k) {
-        Slot& sl = S->slots[k];
-        if (!sl.used) continue;
-        SlotDesc& d = S->desc_h[n];
+    for (int k = 0; k < (int)S->slots.size(); ++k)
+        if (S->slots[k].used) ks.push_back(k);
+    const int n = (int)ks.size();
+    if (n == 0) return HUB_OK;
+    auto shape_key = [&](int k) { return S->slots[k].P.kind * 64 + S->slots[k].P.variant; };
+    std::stable_sort(ks.begin(), ks.end(),
+                     [&](int a, int b) { return shape_key(a) < shape_key(b); });
+    struct Group { int first, count, tiles, kind, variant; };
+    std::vector<Group> groups;
+    int tot_sweep = 0, tot_elem = 0;
+    for (int j = 0; j < n; ++j) {
+        Slot& sl = S->slots[ks[j]];
+        if (groups.empty() || shape_key(ks[groups.back().first]) != shape_key(ks[j]))
+            groups.push_back({j, 0, 0, sl.P.kind, sl.P.variant});
+        Group& gr = groups.back();
+        SlotDesc& d = S->desc_h[j];
         d = SlotDesc{};
         d.g = sl.req.g;
         d.kind = sl.P.kind;
@@ -678,9 +744,9 @@ hub_status run_epoch(hub_server* S) {
         d.tc = sl.P.tc;
         d.sweep_tiles = sl.P.ntiles;
         d.elem_tiles = elem_tiles(d.g.V);
-        d.off_sweep = tot_sweep;
+        d.off_sweep = gr.tiles;
         d.off_elem = tot_elem;
-        d.sc = &S->sc_d[k];
+        d.sc = &S->sc_d[ks[j]];
         d.partials = sl.partials;
         d.phi = sl.phi;
         d.x = sl.x;
@@ -691,24 +757,31 @@ hub_status run_epoch(hub_server* S) {
         d.p1 = sl.p1;
         d.q = sl.q;
         d.xlo = sl.xlo;
-        tot_sweep += d.sweep_tiles;
+        gr.count += 1;
+        gr.tiles += d.sweep_tiles;
         tot_elem += d.elem_tiles;
-        ks.push_back(k);
-        ++n;
     }
-    if (n == 0) return HUB_OK;
     HUB_HIP(hipMemcpyAsync(S->desc_d, S->desc_h, sizeof(SlotDesc) * n, hipMemcpyHostToDevice,
                            S->stream));
     int iters = S->opts.cg.reliable_every;
     const SlotDesc* descp = S->desc_d;
     const bool f16 = S->opts.cg.link == HUB_F16;
     if (S->opts.engine == 1) {
+        // The persistent kernel runs every phase over all solves: offsets of
+        // the sweep phases over all groups.
+        for (int j = 0; j < n; ++j) {
+            S->desc_h[j].off_sweep = tot_sweep;
+            tot_sweep += S->desc_h[j].sweep_tiles;
+        }
+        HUB_HIP(hipMemcpyAsync(S->desc_d, S->desc_h, sizeof(SlotDesc) * n,
+                               hipMemcpyHostToDevice, S->stream));
         k_zero_ctl<<<1, 64, 0, S->stream>>>(S->ctl_d);
         EpochCtl* ctl = S->ctl_d;
         // ~1 s of polling per barrier before giving up (a healthy barrier
         // takes tens of microseconds).
         long spin_limit = 1L << 22;
-        void* args[] = {(void*)&descp, (void*)&n, (void*)&iters, (void*)&tot_sweep,
+        int nn = n;
+        void* args[] = {(void*)&descp, (void*)&nn, (void*)&iters, (void*)&tot_sweep,
                         (void*)&tot_elem, (void*)&ctl, (void*)&spin_limit};
         const void* fn = f16 ? (const void*)k_serve_epoch<Link16>
                              : (const void*)k_serve_epoch<Link32>;
@@ -716,19 +789,29 @@ hub_status run_epoch(hub_server* S) {
                                            kServeLdsBytes, S->stream));
     } else {
         const hipStream_t st = S->stream;
-        for (int it = 0; it < iters; ++it) {
-            if (f16) {
-                k_serve_A<Link16><<<tot_sweep, 256, kServeLdsBytes, st>>>(descp, n);
-                k_serve_finA<Link16><<<n, 256, 0, st>>>(descp);
-            } else {
-                k_serve_A<Link32><<<tot_sweep, 256, kServeLdsBytes, st>>>(descp, n);
-                k_serve_finA<Link32><<<n, 256, 0, st>>>(descp);
+        auto sweeps = [&](bool R) -> hipError_t {
+            for (const Group& gr : groups) {
+                const size_t lds = (R ? 8 : 4) * (size_t)serve_lds_elems(gr.kind, gr.variant);
+                const hipError_t e =
+                    f16 ? launch_serve_sweep<Link16>(R, gr.kind, gr.variant, descp + gr.first,
+                                                     gr.count, gr.tiles, lds, st)
+                        : launch_serve_sweep<Link32>(R, gr.kind, gr.variant, descp + gr.first,
+                                                     gr.count, gr.tiles, lds, st);
+                if (e != hipSuccess) return e;
             }
+            return hipSuccess;
+        };
+        for (int it = 0; it < iters; ++it) {
+            HUB_HIP(sweeps(false));
+            if (f16)
+                k_serve_finA<Link16><<<n, 256, 0, st>>>(descp);
+            else
+                k_serve_finA<Link32><<<n, 256, 0, st>>>(descp);
             k_serve_B<<<tot_elem, 256, 0, st>>>(descp, n);
             k_serve_finB<<<n, 256, 0, st>>>(descp);
         }
         k_serve_fold<<<tot_elem, 256, 0, st>>>(descp, n);
-        k_serve_R<<<tot_sweep, 256, kServeLdsBytes, st>>>(descp, n);
+        HUB_HIP(sweeps(true));
         k_serve_finR<<<n, 256, 0, st>>>(descp);
         HUB_HIP(hipGetLastError());
     }

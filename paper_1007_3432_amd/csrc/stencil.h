@@ -32,15 +32,22 @@ __device__ __forceinline__ void st2(double* p, double a, double b) {
     *reinterpret_cast<double2*>(p) = make_double2(a, b);
 }
 
+// Every link reader splits the access into the load (raw) and the value
+// (val), so that a sweep can issue the loads of a later slice early and form
+// the values when it needs them.
 struct Link64 {
     const double* a;
-    __device__ double operator()(int i, int) const { return a[i]; }
+    using raw_t = double;
+    __device__ double raw(int i) const { return a[i]; }
+    __device__ double val(double r, int) const { return r; }
     __device__ D2 pair(int i, int) const { return ld2(a + i); }
 };
 
 struct Link32 {
     const float* a;
-    __device__ float operator()(int i, int) const { return a[i]; }
+    using raw_t = float;
+    __device__ float raw(int i) const { return a[i]; }
+    __device__ float val(float r, int) const { return r; }
 };
 
 // Stored sin(sigma) in FP16; A = -+(ls + lb * sin sigma) rebuilt in FP32
@@ -48,8 +55,10 @@ struct Link32 {
 struct Link16 {
     const _Float16* sn;
     float ls, lb;
-    __device__ float operator()(int i, int s) const {
-        const float v = fmaf(lb, (float)sn[i], ls);
+    using raw_t = _Float16;
+    __device__ _Float16 raw(int i) const { return sn[i]; }
+    __device__ float val(_Float16 r, int s) const {
+        const float v = fmaf(lb, (float)r, ls);
         return s == 0 ? v : -v;
     }
 };
@@ -58,20 +67,40 @@ struct Link16 {
 // Ops.  Interface:
 //   acc_t, center_t          arithmetic type; per-site state kept from the
 //                            input read to the output write
+//   raw_t, craw_t, lraw_t    what load_h / load_c / lraw return
 //   kReduce, kNP             whether out() feeds a grid reduction of kNP sums
 //   skip()                   block-uniform early exit (device-side state)
 //   begin()                  per-thread set-up from device-side scalars
-//   link(i, s)               A at site i of slice s
-//   in(i)                    input vector value at any site
-//   in_center(i, c)          same, keeping what out() needs in c
-//   out(i, z, v, c, part)    consume z = (Q in)_i, v = in_i; add to part[]
+//   load_h(i), val_h(raw)    input vector value at any site (halo sites):
+//                            the loads, then the value formed from them
+//   load_c(i), val_c(raw, c) the same at a site the tile owns, also loading
+//                            everything out() needs into c
+//   lraw(i), lval(raw, s)    A at site i of slice s, load and value
+//   out(i, z, v, c, part)    consume z = (Q in)_i, v = in_i; stores only;
+//                            add to part[]
 //   finish(total)            thread 0 of the last block: reduced totals
 //   kPair                    FP64 ops that also provide in2 / in_center2 /
 //                            link2 / out2, the same for sites i, i+1 (i even)
 //                            with 16-byte accesses (the d = 1 pair sweep)
-// No op writes a buffer that in() reads, so tiles may run in any order.
+// No op writes a buffer that another site's input reads, so tiles may run in
+// any order; out() at site i writes only buffers that load_c(i) of the same
+// lane has already read.
 
 struct NoCenter {};
+
+template <class Op>
+__device__ __forceinline__ typename Op::acc_t op_in(const Op& op, int i) {
+    return op.val_h(op.load_h(i));
+}
+template <class Op>
+__device__ __forceinline__ typename Op::acc_t op_in_center(const Op& op, int i,
+                                                           typename Op::center_t& c) {
+    return op.val_c(op.load_c(i), c);
+}
+template <class Op>
+__device__ __forceinline__ typename Op::acc_t op_link(const Op& op, int i, int s) {
+    return op.lval(op.lraw(i), s);
+}
 
 // Whether a fold / true-residual kernel of the given mode runs in state done.
 __device__ inline bool mode_runs(int mode, int done) {
@@ -84,6 +113,9 @@ template <class Acc, class Vec, class Lnk>
 struct OpApply {
     using acc_t = Acc;
     using center_t = NoCenter;
+    using raw_t = Vec;
+    using craw_t = Vec;
+    using lraw_t = typename Lnk::raw_t;
     static constexpr bool kReduce = false;
     static constexpr int kNP = 1;
     const Vec* x;
@@ -91,9 +123,12 @@ struct OpApply {
     Lnk lk;
     __device__ bool skip() const { return false; }
     __device__ void begin() {}
-    __device__ Acc link(int i, int s) const { return lk(i, s); }
-    __device__ Acc in(int i) const { return (Acc)x[i]; }
-    __device__ Acc in_center(int i, NoCenter&) const { return (Acc)x[i]; }
+    __device__ Vec load_h(int i) const { return x[i]; }
+    __device__ Acc val_h(Vec r) const { return (Acc)r; }
+    __device__ Vec load_c(int i) const { return x[i]; }
+    __device__ Acc val_c(Vec r, NoCenter&) const { return (Acc)r; }
+    __device__ lraw_t lraw(int i) const { return lk.raw(i); }
+    __device__ Acc lval(lraw_t r, int s) const { return (Acc)lk.val(r, s); }
     __device__ void out(int i, Acc zv, Acc, const NoCenter&, double (&)[kNP]) const {
         z[i] = (Vec)zv;
     }
@@ -117,7 +152,18 @@ struct OpApply {
 template <class Acc, class Vec, class XVec, class Lnk>
 struct OpPhaseA {
     using acc_t = Acc;
-    struct center_t { Acc pold; };
+    struct center_t {
+        Acc pold;
+        XVec xold;
+    };
+    struct raw_t {
+        Vec r, p;
+    };
+    struct craw_t {
+        Vec r, p;
+        XVec x;
+    };
+    using lraw_t = typename Lnk::raw_t;
     static constexpr bool kReduce = true;
     static constexpr int kNP = 1;
     CGScalars* sc;
@@ -140,16 +186,20 @@ struct OpPhaseA {
         alpha = (Acc)sc->alpha;
         gamma = (Acc)sc->gamma;
     }
-    __device__ Acc link(int i, int s) const { return lk(i, s); }
-    __device__ Acc in(int i) const { return gamma * (Acc)r[i] + beta * (Acc)pold[i]; }
-    __device__ Acc in_center(int i, center_t& c) const {
-        c.pold = (Acc)pold[i];
-        return gamma * (Acc)r[i] + beta * c.pold;
+    __device__ raw_t load_h(int i) const { return {r[i], pold[i]}; }
+    __device__ Acc val_h(const raw_t& v) const { return gamma * (Acc)v.r + beta * (Acc)v.p; }
+    __device__ craw_t load_c(int i) const { return {r[i], pold[i], x[i]}; }
+    __device__ Acc val_c(const craw_t& v, center_t& c) const {
+        c.pold = (Acc)v.p;
+        c.xold = v.x;
+        return gamma * (Acc)v.r + beta * c.pold;
     }
+    __device__ lraw_t lraw(int i) const { return lk.raw(i); }
+    __device__ Acc lval(lraw_t v, int s) const { return (Acc)lk.val(v, s); }
     __device__ void out(int i, Acc zv, Acc v, const center_t& c, double (&part)[kNP]) const {
         pnew[i] = (Vec)v;
         q[i] = (Vec)zv;
-        x[i] = (XVec)((Acc)x[i] + alpha * c.pold);
+        x[i] = (XVec)((Acc)c.xold + alpha * c.pold);
         part[0] += (double)v * (double)zv;
     }
     static constexpr bool kPair = sizeof(Acc) == 8 && sizeof(Vec) == 8 && sizeof(XVec) == 8 &&
@@ -195,7 +245,16 @@ struct OpPhaseA {
 template <class RVec>
 struct OpResidual {
     using acc_t = double;
-    using center_t = NoCenter;
+    struct center_t {
+        double phi;
+        RVec pc;
+    };
+    using raw_t = double;
+    struct craw_t {
+        double x, phi;
+        RVec pc;
+    };
+    using lraw_t = double;
     static constexpr bool kReduce = true;
     static constexpr int kNP = 2;
     CGScalars* sc;
@@ -209,21 +268,28 @@ struct OpResidual {
     const RVec* pcur;  // set by begin()
     __device__ bool skip() const { return !mode_runs(mode, sc->done); }
     __device__ void begin() { pcur = (sc->iter & 1) ? pbuf1 : pbuf0; }
-    __device__ double link(int i, int s) const { return lk(i, s); }
-    __device__ double in(int i) const { return x[i]; }
-    __device__ double in_center(int i, NoCenter&) const { return x[i]; }
-    __device__ void out(int i, double zv, double, const NoCenter&, double (&part)[kNP]) const {
-        const double d = phi[i] - zv;
+    __device__ double load_h(int i) const { return x[i]; }
+    __device__ double val_h(double v) const { return v; }
+    __device__ craw_t load_c(int i) const { return {x[i], phi[i], pcur[i]}; }
+    __device__ double val_c(const craw_t& v, center_t& c) const {
+        c.phi = v.phi;
+        c.pc = v.pc;
+        return v.x;
+    }
+    __device__ double lraw(int i) const { return lk.raw(i); }
+    __device__ double lval(double v, int s) const { return lk.val(v, s); }
+    __device__ void out(int i, double zv, double, const center_t& c, double (&part)[kNP]) const {
+        const double d = c.phi - zv;
         const RVec rd = (RVec)d;
         r[i] = rd;
         part[0] += d * d;
-        part[1] += (double)rd * (double)pcur[i];
+        part[1] += (double)rd * (double)c.pc;
     }
     static constexpr bool kPair = sizeof(RVec) == 8;
     __device__ D2 in2(int i) const { return ld2(x + i); }
-    __device__ D2 in_center2(int i, NoCenter&, NoCenter&) const { return ld2(x + i); }
+    __device__ D2 in_center2(int i, center_t&, center_t&) const { return ld2(x + i); }
     __device__ D2 link2(int i, int s) const { return lk.pair(i, s); }
-    __device__ void out2(int i, D2 zv, D2, const NoCenter&, const NoCenter&,
+    __device__ void out2(int i, D2 zv, D2, const center_t&, const center_t&,
                          double (&part)[kNP]) const {
         const D2 f = ld2(phi + i), pc = ld2((const double*)pcur + i);
         const double d0 = f.a - zv.a, d1 = f.b - zv.b;
@@ -271,6 +337,9 @@ struct OpResidual {
 struct OpChebW {
     using acc_t = double;
     using center_t = NoCenter;
+    using raw_t = double;
+    using craw_t = double;
+    using lraw_t = double;
     static constexpr bool kReduce = false;
     static constexpr int kNP = 1;
     const CGScalars* sc;
@@ -279,9 +348,12 @@ struct OpChebW {
     Link64 lk;
     __device__ bool skip() const { return sc && sc->done != kRunning; }
     __device__ void begin() {}
-    __device__ double link(int i, int s) const { return lk(i, s); }
-    __device__ double in(int i) const { return v[i]; }
-    __device__ double in_center(int i, NoCenter&) const { return v[i]; }
+    __device__ double load_h(int i) const { return v[i]; }
+    __device__ double val_h(double r) const { return r; }
+    __device__ double load_c(int i) const { return v[i]; }
+    __device__ double val_c(double r, NoCenter&) const { return r; }
+    __device__ double lraw(int i) const { return lk.raw(i); }
+    __device__ double lval(double r, int s) const { return lk.val(r, s); }
     __device__ void out(int i, double zv, double, const NoCenter&, double (&)[kNP]) const {
         w[i] = zv;
     }
@@ -299,7 +371,14 @@ struct OpChebW {
 template <bool kDot>
 struct OpChebZ {
     using acc_t = double;
-    using center_t = NoCenter;
+    struct center_t {
+        double v, r;
+    };
+    using raw_t = double;
+    struct craw_t {
+        double w, v, r;
+    };
+    using lraw_t = double;
     static constexpr bool kReduce = kDot;
     static constexpr int kNP = 1;
     CGScalars* sc;
@@ -311,19 +390,26 @@ struct OpChebZ {
     Link64 lk;
     __device__ bool skip() const { return sc && sc->done != kRunning; }
     __device__ void begin() {}
-    __device__ double link(int i, int s) const { return lk(i, s); }
-    __device__ double in(int i) const { return w[i]; }
-    __device__ double in_center(int i, NoCenter&) const { return w[i]; }
-    __device__ void out(int i, double zv, double wv, const NoCenter&, double (&part)[kNP]) const {
-        const double o = c2 * zv + c1 * wv + c0 * v[i];
+    __device__ double load_h(int i) const { return w[i]; }
+    __device__ double val_h(double x) const { return x; }
+    __device__ craw_t load_c(int i) const { return {w[i], v[i], kDot ? r[i] : 0.0}; }
+    __device__ double val_c(const craw_t& x, center_t& c) const {
+        c.v = x.v;
+        c.r = x.r;
+        return x.w;
+    }
+    __device__ double lraw(int i) const { return lk.raw(i); }
+    __device__ double lval(double x, int s) const { return lk.val(x, s); }
+    __device__ void out(int i, double zv, double wv, const center_t& c, double (&part)[kNP]) const {
+        const double o = c2 * zv + c1 * wv + c0 * c.v;
         vout[i] = o;
-        if constexpr (kDot) part[0] += r[i] * o;
+        if constexpr (kDot) part[0] += c.r * o;
     }
     static constexpr bool kPair = true;
     __device__ D2 in2(int i) const { return ld2(w + i); }
-    __device__ D2 in_center2(int i, NoCenter&, NoCenter&) const { return ld2(w + i); }
+    __device__ D2 in_center2(int i, center_t&, center_t&) const { return ld2(w + i); }
     __device__ D2 link2(int i, int s) const { return lk.pair(i, s); }
-    __device__ void out2(int i, D2 zv, D2 wv, const NoCenter&, const NoCenter&,
+    __device__ void out2(int i, D2 zv, D2 wv, const center_t&, const center_t&,
                          double (&part)[kNP]) const {
         const D2 vv = ld2(v + i);
         const double o0 = c2 * zv.a + c1 * wv.a + c0 * vv.a;
@@ -420,26 +506,26 @@ __device__ __forceinline__ void tile_mtm_d1(const Geom& g, const Op& op, int til
     for (int rho = 0; rho < TT + 2; ++rho) {
         const int row = wrap1(s0 - 1 + (rho < h + 2 ? rho : h + 1), nt) * nx;
         if (rho >= 1 && rho <= TT)
-            xv[rho] = op.in_center(row + site, cen[rho - 1]);
+            xv[rho] = op_in_center(op, row + site, cen[rho - 1]);
         else
-            xv[rho] = op.in(row + site);
+            xv[rho] = op_in(op, row + site);
     }
 #pragma unroll
     for (int rho = 0; rho < TT + 1; ++rho) {
         const int sl = wrap1(s0 + (rho <= h ? rho : h), nt);
-        av[rho] = op.link(sl * nx + site, sl);
+        av[rho] = op_link(op, sl * nx + site, sl);
     }
     if (left || right) {
 #pragma unroll
         for (int rho = 0; rho < TT + 2; ++rho) {
             const int row = wrap1(s0 - 1 + (rho < h + 2 ? rho : h + 1), nt) * nx;
-            x1[rho] = op.in(row + h1);
-            x2[rho] = op.in(row + h2);
+            x1[rho] = op_in(op, row + h1);
+            x2[rho] = op_in(op, row + h2);
         }
 #pragma unroll
         for (int rho = 0; rho < TT + 1; ++rho) {
             const int sl = wrap1(s0 + (rho <= h ? rho : h), nt);
-            a1[rho] = op.link(sl * nx + h1, sl);
+            a1[rho] = op_link(op, sl * nx + h1, sl);
         }
     }
 
@@ -550,13 +636,13 @@ __device__ __forceinline__ void tile_mtm_d1p(const Geom& g, const Op& op, int ti
 #pragma unroll
         for (int rho = 0; rho < TT + 2; ++rho) {
             const int row = wrap1(s0 - 1 + (rho < h + 2 ? rho : h + 1), nt) * nx;
-            x1[rho] = op.in(row + h1);
-            x2[rho] = op.in(row + h2);
+            x1[rho] = op_in(op, row + h1);
+            x2[rho] = op_in(op, row + h2);
         }
 #pragma unroll
         for (int rho = 0; rho < TT + 1; ++rho) {
             const int sl = wrap1(s0 + (rho <= h ? rho : h), nt);
-            a1[rho] = op.link(sl * nx + h1, sl);
+            a1[rho] = op_link(op, sl * nx + h1, sl);
         }
     }
 
@@ -615,39 +701,56 @@ __global__ __launch_bounds__(TX / 2) void k_mtm_d1p(Geom g, Op op, int tiles_x, 
 // ---------------------------------------------------------------------------
 // Fused Q = M^T M sweep for d = 3, nx = NX.
 //
-// A block owns a tile of whole x rows (NX sites) times TY y-rows times TZ
-// z-planes and marches over a chunk of consecutive time slices.  At step s
-// it stages the input of slice s+1 on the tile plus a two-site halo in y and
-// z in LDS, forms y_{s+1} = W x_{s+1} + A_{s+1} x_s on the tile plus a
-// one-site halo (a 2-deep LDS ring holds y_s and y_{s+1}), and emits
-// z_s = W y_s + A_{s+1} y_{s+1} on the tile.  x is periodic inside a row, so
-// rows need no halo.  The tile's PZ = NX*TY*TZ sites are owned by fixed
-// lanes (site q by lane q mod 256), which keep their input value, op state
-// and A in registers from the load of slice s+1 to the output of slice s+1.
+// A block of BLOCK lanes owns a tile of whole x rows (NX sites) times TY
+// y-rows times TZ z-planes and marches over a chunk of consecutive time
+// slices.  Step s (z emitted on slice s):
+//   1. the input of slice s+1, loaded one step earlier, goes into LDS (X) on
+//      the tile plus a two-site halo in y and z (x is periodic inside a row,
+//      so rows need no halo), and the loads of slice s+2 are issued;
+//   2. y_{s+1} = W x_{s+1} + A_{s+1} x_s is formed in registers on the tile
+//      and on its one-site halo;
+//   3. z_s = W y_s + A_{s+1} y_{s+1} is formed on the tile, with y_s from
+//      LDS (Y) and y_{s+1} from the lane's registers, and handed to the op;
+//   4. y_{s+1} replaces y_s in Y.
+// Two barriers per step.  The tile's PZ = NX*TY*TZ sites are owned by fixed
+// lanes (site q by lane q mod BLOCK), which keep their input value and op
+// state in registers from the load of slice s+1 to the output of slice s+1,
+// so the op's output is stores only.  The loads of a slice are issued a step
+// before it is staged and stay in flight while the slice before it is
+// computed: a barrier on gfx950 waits for LDS traffic only, not for
+// outstanding global loads.
 template <int NX, int TY, int TZ>
 constexpr int d3_lds_elems() {
-    return NX * (TY + 4) * (TZ + 4) + 2 * NX * (TY + 2) * (TZ + 2);
+    // X, Y and one spare element that lanes without a halo position write
+    // to, so that every LDS write is unconditional (no divergent branch in
+    // the march, whose join would make the compiler wait for all
+    // outstanding memory operations, stores included).
+    return NX * (TY + 4) * (TZ + 4) + NX * (TY + 2) * (TZ + 2) + 1;
 }
 
-// One tile b of the sweep (block of 256 lanes); adds this lane's share of
+// One tile b of the sweep (block of BLOCK lanes); adds this lane's share of
 // the op's sums to part.  lds: d3_lds_elems<NX, TY, TZ>() elements.
-template <class Op, int NX, int TY, int TZ>
+template <class Op, int NX, int TY, int TZ, int BLOCK>
 __device__ __forceinline__ void tile_mtm_d3(const Geom& g, const Op& op, int tiles_y,
                                             int tiles_z, int tc, int b,
                                             typename Op::acc_t* lds,
                                             double (&part)[Op::kNP]) {
     using Acc = typename Op::acc_t;
     using Center = typename Op::center_t;
+    using Raw = typename Op::raw_t;
+    using CRaw = typename Op::craw_t;
+    using LRaw = typename Op::lraw_t;
     constexpr int XY = TY + 4, XZ = TZ + 4, YY = TY + 2, YZ = TZ + 2;
-    constexpr int PX = NX * XY * XZ, PY = NX * YY * YZ, PZ = NX * TY * TZ;
+    constexpr int PX = NX * XY * XZ, PZ = NX * TY * TZ;
     static_assert((NX & (NX - 1)) == 0, "NX must be a power of two");
-    static_assert(PZ % 256 == 0, "tile must be whole multiples of the block");
-    constexpr int NC = PZ / 256;
+    static_assert(PZ % BLOCK == 0, "tile must be whole multiples of the block");
+    constexpr int NC = PZ / BLOCK;
     // Halo rows (y, z pairs outside the tile) of the X and Y stages.
     constexpr int HRX = XY * XZ - TY * TZ, HRY = YY * YZ - TY * TZ;
-    constexpr int NHX = (NX * HRX + 255) / 256, NHY = (NX * HRY + 255) / 256;
+    constexpr int NHX = (NX * HRX + BLOCK - 1) / BLOCK, NHY = (NX * HRY + BLOCK - 1) / BLOCK;
     Acc* X = lds;
-    Acc (*Y)[PY] = reinterpret_cast<Acc (*)[PY]>(lds + PX);
+    Acc* Y = lds + PX;
+    constexpr int kSink = PX + NX * YY * YZ;  // spare element, index into lds
     const int nt = g.nt, vs = g.vs;
     const int iy = b % tiles_y;
     b /= tiles_y;
@@ -662,7 +765,7 @@ __device__ __forceinline__ void tile_mtm_d3(const Geom& g, const Op& op, int til
     int cn[NC], cx[NC], cxi[NC], cyi[NC];
 #pragma unroll
     for (int k = 0; k < NC; ++k) {
-        const int q = t + 256 * k;
+        const int q = t + BLOCK * k;
         const int x = q % NX, r = q / NX, ty = r % TY, tz = r / TY;
         cx[k] = x;
         cn[k] = x + NX * ((y0 + ty) + NX * (z0 + tz));
@@ -676,7 +779,7 @@ __device__ __forceinline__ void tile_mtm_d3(const Geom& g, const Op& op, int til
     bool hxo[NHX];
 #pragma unroll
     for (int k = 0; k < NHX; ++k) {
-        int q = t + 256 * k;
+        int q = t + BLOCK * k;
         hxo[k] = q < NX * HRX;
         if (!hxo[k]) q = NX * HRX - 1;
         const int x = q % NX, hr = q / NX;
@@ -692,7 +795,7 @@ __device__ __forceinline__ void tile_mtm_d3(const Geom& g, const Op& op, int til
             zx = 2 + r / 4;
             yx = c < 2 ? c : TY + c;
         }
-        hxi[k] = x + NX * (yx + XY * zx);
+        hxi[k] = hxo[k] ? x + NX * (yx + XY * zx) : kSink;
         hxs[k] = x + NX * (wrap1(y0 - 2 + yx, NX) + NX * wrap1(z0 - 2 + zx, NX));
     }
     // Y halo positions: spatial index, Y index, X index of the same site.
@@ -700,7 +803,7 @@ __device__ __forceinline__ void tile_mtm_d3(const Geom& g, const Op& op, int til
     bool hyo[NHY];
 #pragma unroll
     for (int k = 0; k < NHY; ++k) {
-        int q = t + 256 * k;
+        int q = t + BLOCK * k;
         hyo[k] = q < NX * HRY;
         if (!hyo[k]) q = NX * HRY - 1;
         const int x = q % NX, hr = q / NX;
@@ -714,7 +817,7 @@ __device__ __forceinline__ void tile_mtm_d3(const Geom& g, const Op& op, int til
             yy = (r & 1) ? TY + 1 : 0;
         }
         hyc[k] = x;
-        hyi[k] = x + NX * (yy + YY * zz);
+        hyi[k] = hyo[k] ? x + NX * (yy + YY * zz) : kSink - PX;
         hyx[k] = x + NX * ((yy + 1) + XY * (zz + 1));
         hys[k] = x + NX * (wrap1(y0 - 1 + yy, NX) + NX * wrap1(z0 - 1 + zz, NX));
     }
@@ -725,92 +828,113 @@ __device__ __forceinline__ void tile_mtm_d3(const Geom& g, const Op& op, int til
                                X[j - NX * XY] + X[j + NX * XY]);
     };
 
-    Acc xc_cur[NC], xc_nxt[NC], ac[NC];
-    Center cc_cur[NC], cc_nxt[NC];
-    Acc xh[NHY], ah[NHY];
-
-    // Stage slice s: every global load first, then the LDS writes.
-    auto load_slice = [&](int s, Acc (&xc)[NC], Center (&cc)[NC]) {
-        const int off = vs * s;
-        Acc xv[NHX];
+    // Loads of one slice, issued a step before they are used.
+    CRaw pc[NC];
+    LRaw pa[NC];
+    Raw ph[NHX];
+    LRaw pah[NHY];
+    auto prefetch = [&](int sl) {
+        const int off = vs * sl;
 #pragma unroll
         for (int k = 0; k < NC; ++k) {
-            xc[k] = op.in_center(cn[k] + off, cc[k]);
-            ac[k] = op.link(cn[k] + off, s);
+            pc[k] = op.load_c(cn[k] + off);
+            pa[k] = op.lraw(cn[k] + off);
         }
 #pragma unroll
-        for (int k = 0; k < NHX; ++k) xv[k] = op.in(hxs[k] + off);
+        for (int k = 0; k < NHX; ++k) ph[k] = op.load_h(hxs[k] + off);
 #pragma unroll
-        for (int k = 0; k < NHY; ++k) ah[k] = op.link(hys[k] + off, s);
-#pragma unroll
-        for (int k = 0; k < NC; ++k) X[cxi[k]] = xc[k];
-#pragma unroll
-        for (int k = 0; k < NHX; ++k)
-            if (hxo[k]) X[hxi[k]] = xv[k];
+        for (int k = 0; k < NHY; ++k) pah[k] = op.lraw(hys[k] + off);
     };
-    // y of the slice now in X into Y[buf]; xprev_c: previous slice at the
-    // owned sites; xh: previous slice at the halo positions (replaced by the
-    // current one).
-    auto form_y = [&](int buf, const Acc (&xprev_c)[NC]) {
-        Acc* Yb = Y[buf];
+    // x_s, x_{s+1} and op state at the owned sites; x_s at the Y-halo
+    // positions; A_{s+1} at both.
+    Acc xs_c[NC], xn_c[NC], an_c[NC], xs_h[NHY], an_h[NHY];
+    Center cs_c[NC], cn_c[NC];
+    // The prefetched slice sl into X, xn_c / cn_c and an_c / an_h.
+    auto stage = [&](int sl) {
 #pragma unroll
-        for (int k = 0; k < NC; ++k)
-            Yb[cyi[k]] = wx(cx[k], cxi[k]) + ac[k] * xprev_c[k];
-#pragma unroll
-        for (int k = 0; k < NHY; ++k) {
-            const Acc v = wx(hyc[k], hyx[k]) + ah[k] * xh[k];
-            if (hyo[k]) Yb[hyi[k]] = v;
-            xh[k] = X[hyx[k]];
+        for (int k = 0; k < NC; ++k) {
+            xn_c[k] = op.val_c(pc[k], cn_c[k]);
+            an_c[k] = op.lval(pa[k], sl);
+            X[cxi[k]] = xn_c[k];
         }
+#pragma unroll
+        for (int k = 0; k < NHX; ++k) X[hxi[k]] = op.val_h(ph[k]);
+#pragma unroll
+        for (int k = 0; k < NHY; ++k) an_h[k] = op.lval(pah[k], sl);
     };
 
-    // Prologue: slice s0-1 at owned and halo positions, then y_{s0}.
+    // Prologue: x_{s0-1} at the owned and Y-halo positions, slice s0 into X,
+    // y_{s0} into Y, slice s0+1 in flight.
     {
         const int offm = vs * wrap1(s0 - 1, nt);
-        Acc xp_c[NC];
 #pragma unroll
-        for (int k = 0; k < NC; ++k) xp_c[k] = op.in(cn[k] + offm);
+        for (int k = 0; k < NC; ++k) xs_c[k] = op_in(op, cn[k] + offm);
 #pragma unroll
-        for (int k = 0; k < NHY; ++k) xh[k] = op.in(hys[k] + offm);
-        load_slice(s0, xc_cur, cc_cur);
+        for (int k = 0; k < NHY; ++k) xs_h[k] = op_in(op, hys[k] + offm);
+        prefetch(s0);
+        stage(s0);
+        prefetch(wrap1(s0 + 1, nt));
         __syncthreads();
-        form_y(0, xp_c);
+#pragma unroll
+        for (int k = 0; k < NC; ++k) Y[cyi[k]] = wx(cx[k], cxi[k]) + an_c[k] * xs_c[k];
+#pragma unroll
+        for (int k = 0; k < NHY; ++k) {
+            Y[hyi[k]] = wx(hyc[k], hyx[k]) + an_h[k] * xs_h[k];
+            xs_h[k] = X[hyx[k]];
+        }
+#pragma unroll
+        for (int k = 0; k < NC; ++k) {
+            xs_c[k] = xn_c[k];
+            cs_c[k] = cn_c[k];
+        }
         __syncthreads();
     }
 
     for (int r = 0; r < h; ++r) {
         const int s = s0 + r;
-        load_slice(wrap1(s + 1, nt), xc_nxt, cc_nxt);
+        stage(wrap1(s + 1, nt));
+        if (r + 1 < h) prefetch(wrap1(s + 2, nt));
         __syncthreads();
-        form_y((r + 1) & 1, xc_cur);
-        __syncthreads();
-        const Acc* Yc = Y[r & 1];
-        const Acc* Yn = Y[(r + 1) & 1];
+        Acc yo[NC], yh[NHY];
+#pragma unroll
+        for (int k = 0; k < NC; ++k) yo[k] = wx(cx[k], cxi[k]) + an_c[k] * xs_c[k];
+#pragma unroll
+        for (int k = 0; k < NHY; ++k) {
+            yh[k] = wx(hyc[k], hyx[k]) + an_h[k] * xs_h[k];
+            xs_h[k] = X[hyx[k]];
+        }
 #pragma unroll
         for (int k = 0; k < NC; ++k) {
             const int j = cyi[k], x = cx[k];
             const int xm = (x - 1) & (NX - 1), xp = (x + 1) & (NX - 1);
-            const Acc zv = Yc[j] - kappa * (Yc[j - x + xm] + Yc[j - x + xp] + Yc[j - NX] +
-                                            Yc[j + NX] + Yc[j - NX * YY] + Yc[j + NX * YY]) +
-                           ac[k] * Yn[j];
-            op.out(cn[k] + vs * s, zv, xc_cur[k], cc_cur[k], part);
-            xc_cur[k] = xc_nxt[k];
-            cc_cur[k] = cc_nxt[k];
+            const Acc zv = Y[j] - kappa * (Y[j - x + xm] + Y[j - x + xp] + Y[j - NX] +
+                                           Y[j + NX] + Y[j - NX * YY] + Y[j + NX * YY]) +
+                           an_c[k] * yo[k];
+            op.out(cn[k] + vs * s, zv, xs_c[k], cs_c[k], part);
         }
+        __syncthreads();
+#pragma unroll
+        for (int k = 0; k < NC; ++k) {
+            Y[cyi[k]] = yo[k];
+            xs_c[k] = xn_c[k];
+            cs_c[k] = cn_c[k];
+        }
+#pragma unroll
+        for (int k = 0; k < NHY; ++k) Y[hyi[k]] = yh[k];
     }
 }
 
-template <class Op, int NX, int TY, int TZ>
-__global__ __launch_bounds__(256) void k_mtm_d3(Geom g, Op op, int tiles_y, int tiles_z,
-                                                int tc, double* partials) {
+template <class Op, int NX, int TY, int TZ, int BLOCK>
+__global__ __launch_bounds__(BLOCK) void k_mtm_d3(Geom g, Op op, int tiles_y, int tiles_z,
+                                                  int tc, double* partials) {
     using Acc = typename Op::acc_t;
     __shared__ Acc lds[d3_lds_elems<NX, TY, TZ>()];
     if (op.skip()) return;
     op.begin();
     const int b = xcd_remap(blockIdx.x, gridDim.x);
     double part[Op::kNP] = {};
-    tile_mtm_d3<Op, NX, TY, TZ>(g, op, tiles_y, tiles_z, tc, b, lds, part);
-    if constexpr (Op::kReduce) deposit<256, Op::kNP>(part, partials, b);
+    tile_mtm_d3<Op, NX, TY, TZ, BLOCK>(g, op, tiles_y, tiles_z, tc, b, lds, part);
+    if constexpr (Op::kReduce) deposit<BLOCK, Op::kNP>(part, partials, b);
 }
 
 // ---------------------------------------------------------------------------
@@ -827,11 +951,11 @@ __device__ inline typename Op::acc_t gen_M_at(const Geom& g, const Op& op, int i
         const int c = (n / stride) % g.nx;
         const int cp = c + 1 == g.nx ? 0 : c + 1;
         const int cm = c == 0 ? g.nx - 1 : c - 1;
-        hop += op.in(i + (cp - c) * stride) + op.in(i + (cm - c) * stride);
+        hop += op_in(op, i + (cp - c) * stride) + op_in(op, i + (cm - c) * stride);
         stride *= g.nx;
     }
     const int sm = s == 0 ? g.nt - 1 : s - 1;
-    return op.in(i) - (Acc)g.kappa * hop + op.link(i, s) * op.in(n + sm * g.vs);
+    return op_in(op, i) - (Acc)g.kappa * hop + op_link(op, i, s) * op_in(op, n + sm * g.vs);
 }
 
 template <class Op>
@@ -864,9 +988,9 @@ __global__ __launch_bounds__(256) void k_gen_pass2(Geom g, Op op,
         }
         const int sp = s == g.nt - 1 ? 0 : s + 1;
         const int ip = n + sp * g.vs;
-        const Acc zv = y[i] - (Acc)g.kappa * hop + op.link(ip, sp) * y[ip];
+        const Acc zv = y[i] - (Acc)g.kappa * hop + op_link(op, ip, sp) * y[ip];
         typename Op::center_t c;
-        const Acc v = op.in_center(i, c);
+        const Acc v = op_in_center(op, i, c);
         op.out(i, zv, v, c, part);
     }
     if constexpr (Op::kReduce) deposit<256, Op::kNP>(part, partials, blockIdx.x);
@@ -891,11 +1015,11 @@ __global__ __launch_bounds__(256) void k_apply_M(Geom g, Lnk lk, const Vec* x, V
     Acc v = (Acc)x[i] - (Acc)g.kappa * hop;
     if (!TRANSPOSE) {
         const int sm = s == 0 ? g.nt - 1 : s - 1;
-        v += (Acc)lk(i, s) * (Acc)x[n + sm * g.vs];
+        v += (Acc)lk.val(lk.raw(i), s) * (Acc)x[n + sm * g.vs];
     } else {
         const int sp = s == g.nt - 1 ? 0 : s + 1;
         const int ip = n + sp * g.vs;
-        v += (Acc)lk(ip, sp) * (Acc)x[ip];
+        v += (Acc)lk.val(lk.raw(ip), sp) * (Acc)x[ip];
     }
     y[i] = (Vec)v;
 }

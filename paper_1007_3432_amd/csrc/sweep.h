@@ -19,12 +19,17 @@ static constexpr D1Shape kD1Shapes[kD1_Count] = {
     {256, 8}, {128, 8}, {64, 8}, {256, 4}, {256, 16}, {128, 16},
     {256, 2}, {256, 1}, {128, 4}, {64, 4}};
 
-// Tile shapes of the fused d = 3 kernel: whole rows of NX x TY x TZ.
+// Tile shapes of the fused d = 3 kernel: whole rows of NX x TY x TZ, swept
+// by blocks of `block` lanes.  Mixed-precision solves (and with them the
+// serving kernel, which must take the same steps) use 256-lane tiles only.
 enum D3Tile { kD3_8x8x8 = 0, kD3_16x4x4, kD3_16x8x8, kD3_32x4x4, kD3_32x8x4, kD3_64x4x4,
-              kD3_Count };
-struct D3Shape { int nx, ty, tz; };
+              kD3_16x8x4, kD3_32x8x8_512, kD3_64x4x4_512, kD3_64x8x4_512, kD3_16x8x8_512,
+              kD3_32x8x4_512, kD3_32x4x4_512, kD3_16x8x4_512, kD3_8x8x8_512, kD3_Count };
+struct D3Shape { int nx, ty, tz, block; };
 static constexpr D3Shape kD3Shapes[kD3_Count] = {
-    {8, 8, 8}, {16, 4, 4}, {16, 8, 8}, {32, 4, 4}, {32, 8, 4}, {64, 4, 4}};
+    {8, 8, 8, 256}, {16, 4, 4, 256}, {16, 8, 8, 256}, {32, 4, 4, 256}, {32, 8, 4, 256},
+    {64, 4, 4, 256}, {16, 8, 4, 256}, {32, 8, 8, 512}, {64, 4, 4, 512}, {64, 8, 4, 512},
+    {16, 8, 8, 512}, {32, 8, 4, 512}, {32, 4, 4, 512}, {16, 8, 4, 512}, {8, 8, 8, 512}};
 
 enum SweepKind { kSweepD1 = 0, kSweepD3, kSweepGeneric };
 
@@ -45,7 +50,7 @@ struct SweepPlan {
 };
 
 // Tuning aids: HUB_D1_TILE=<TX>x<TT>,
-// HUB_D3_TILE=<NX>x<TY>x<TZ>, HUB_D3_TC=<slices per block>, HUB_SWEEP=generic.
+// HUB_D3_TILE=<NX>x<TY>x<TZ>[@512], HUB_D3_TC=<slices per block>, HUB_SWEEP=generic.
 inline const char* env_or_null(const char* k) { return std::getenv(k); }
 
 inline int d1_tile_override() {
@@ -68,8 +73,12 @@ inline int d3_tile_override() {
         if (!e) return -1;
         for (int k = 0; k < kD3_Count; ++k) {
             char buf[32];
-            std::snprintf(buf, sizeof(buf), "%dx%dx%d", kD3Shapes[k].nx, kD3Shapes[k].ty,
-                          kD3Shapes[k].tz);
+            if (kD3Shapes[k].block == 256)
+                std::snprintf(buf, sizeof(buf), "%dx%dx%d", kD3Shapes[k].nx, kD3Shapes[k].ty,
+                              kD3Shapes[k].tz);
+            else
+                std::snprintf(buf, sizeof(buf), "%dx%dx%d@%d", kD3Shapes[k].nx, kD3Shapes[k].ty,
+                              kD3Shapes[k].tz, kD3Shapes[k].block);
             if (std::strcmp(buf, e) == 0) return k;
         }
         return -1;
@@ -131,13 +140,18 @@ inline SweepPlan plan_sweep(const Geom& g, bool f64) {
         p.grid = p.ntiles;
     } else if (!force_generic() && g.d == 3) {
         int v = d3_tile_override();
-        if (v >= 0 && kD3Shapes[v].nx != g.nx) v = -1;
+        if (v >= 0 && (kD3Shapes[v].nx != g.nx || (!f64 && kD3Shapes[v].block != 256))) v = -1;
         if (v < 0) {
+            // Measured on MI355X (bare FP64 and FP32 sweeps on 8^3 x 80,
+            // 16^3 x 160, 32^3 x 256, 64^3 x 32): FP64 sweeps run best on
+            // 512-lane blocks for nx = 16, 32 (fewer registers per lane than
+            // the 256-lane tiles, whose FP64 CG variant needs 256 VGPRs);
+            // mixed-precision plans stay on 256-lane tiles.
             switch (g.nx) {
                 case 8: v = kD3_8x8x8; break;
-                case 16: v = kD3_16x4x4; break;
-                case 32: v = kD3_32x8x4; break;
-                case 64: v = kD3_64x4x4; break;
+                case 16: v = f64 ? kD3_16x8x4_512 : kD3_16x4x4; break;
+                case 32: v = f64 ? kD3_32x8x4_512 : kD3_32x8x4; break;
+                case 64: v = f64 ? kD3_64x4x4_512 : kD3_64x4x4; break;
                 default: v = -1;
             }
         }
@@ -148,10 +162,11 @@ inline SweepPlan plan_sweep(const Geom& g, bool f64) {
             p.tiles_y = g.nx / sh.ty;
             p.tiles_z = g.nx / sh.tz;
             const int tiles = p.tiles_y * p.tiles_z;
-            // Aim at ~1024 blocks (four per CU); longer marches amortise the
-            // prologue slice, shorter ones leave more blocks to hide latency.
-            int tc = ceil_div(g.nt * tiles, 1024);
-            tc = tc < 2 ? 2 : (tc > 16 ? 16 : tc);
+            // Slices per block: the sweeps ran best with about 128K lanes in
+            // the grid (one 512-lane or two 256-lane blocks per CU), long
+            // marches amortising each block's prologue slice.
+            long long tcl = ((long long)g.nt * tiles * sh.block + 131071) / 131072;
+            int tc = (int)(tcl < 2 ? 2 : (tcl > 16 ? 16 : tcl));
             tc = env_int("HUB_D3_TC", tc);
             if (tc < 1) tc = 1;
             p.tc = tc;
@@ -223,17 +238,26 @@ hub_status launch_q(const Geom& g, const SweepPlan& P, const Op& op,
         if (g.nx != kD3Shapes[P.variant].nx)
             return set_error(HUB_E_INVALID, "internal: d=3 tile does not fit nx");
         switch (P.variant) {
-#define HUB_D3_CASE(K, NX, TY, TZ)                                                      \
-    case K:                                                                             \
-        k_mtm_d3<Op, NX, TY, TZ><<<P.grid, 256, 0, st>>>(g, op, P.tiles_y, P.tiles_z,    \
-                                                          P.tc, partials);               \
+#define HUB_D3_CASE(K, NX, TY, TZ, B)                                                    \
+    case K:                                                                              \
+        k_mtm_d3<Op, NX, TY, TZ, B><<<P.grid, B, 0, st>>>(g, op, P.tiles_y, P.tiles_z,    \
+                                                           P.tc, partials);               \
         break;
-            HUB_D3_CASE(kD3_8x8x8, 8, 8, 8)
-            HUB_D3_CASE(kD3_16x4x4, 16, 4, 4)
-            HUB_D3_CASE(kD3_16x8x8, 16, 8, 8)
-            HUB_D3_CASE(kD3_32x4x4, 32, 4, 4)
-            HUB_D3_CASE(kD3_32x8x4, 32, 8, 4)
-            HUB_D3_CASE(kD3_64x4x4, 64, 4, 4)
+            HUB_D3_CASE(kD3_8x8x8, 8, 8, 8, 256)
+            HUB_D3_CASE(kD3_16x4x4, 16, 4, 4, 256)
+            HUB_D3_CASE(kD3_16x8x8, 16, 8, 8, 256)
+            HUB_D3_CASE(kD3_32x4x4, 32, 4, 4, 256)
+            HUB_D3_CASE(kD3_32x8x4, 32, 8, 4, 256)
+            HUB_D3_CASE(kD3_64x4x4, 64, 4, 4, 256)
+            HUB_D3_CASE(kD3_16x8x4, 16, 8, 4, 256)
+            HUB_D3_CASE(kD3_32x8x8_512, 32, 8, 8, 512)
+            HUB_D3_CASE(kD3_64x4x4_512, 64, 4, 4, 512)
+            HUB_D3_CASE(kD3_64x8x4_512, 64, 8, 4, 512)
+            HUB_D3_CASE(kD3_16x8x8_512, 16, 8, 8, 512)
+            HUB_D3_CASE(kD3_32x8x4_512, 32, 8, 4, 512)
+            HUB_D3_CASE(kD3_32x4x4_512, 32, 4, 4, 512)
+            HUB_D3_CASE(kD3_16x8x4_512, 16, 8, 4, 512)
+            HUB_D3_CASE(kD3_8x8x8_512, 8, 8, 8, 512)
 #undef HUB_D3_CASE
             default:
                 return set_error(HUB_E_INVALID, "internal: bad d=3 tile variant");
