@@ -1,16 +1,27 @@
 // Conjugate gradient on Q = M^T M (Sec. 4.1): FP64 Hestenes-Stiefel CG and
 // mixed-precision CG with FP64 reliable updates, all state device-resident.
 //
-// One iteration is two kernels:
-//   A  p_new = r + beta p_old, q = Q p_new, x += alpha_prev p_old, p.q
-//      (the fused sweep with OpPhaseA); its last block sets alpha = rho/p.q
-//   B  r -= alpha q, r.r; its last block sets beta, rho and the done flag
-// Every kernel reads the scalars it needs from device memory and returns at
-// once when the solve has finished, so the host enqueues whole chunks of
-// iterations and looks at the state only between chunks (one chunk ahead).
-// A chunk ends with a fold (x += pending alpha p [+ x_lo]) and an FP64
-// true-residual sweep: always in the mixed solver (the reliable update),
-// only after an iterated convergence in the FP64 solver.
+// One iteration is three kernels around two grid-wide reductions:
+//   A  p_new = gamma r + beta p_old, q = Q p_new, x += alpha_prev p_old, and
+//      one p.q deposit per tile (the fused sweep with OpPhaseA);
+//   B  every block adds all p.q deposits itself (in one fixed order, so all
+//      blocks get the same bits), sets alpha = rho / p.q, then r -= alpha q
+//      and one r.r deposit per tile; its loads of r and q are issued before
+//      that sum, so the sum costs about nothing;
+//   F  one block adds the r.r deposits and sets rho, beta, the iteration
+//      count and the convergence decision.
+// (Taking F into the next A as well was measured slower: A's loads depend
+// on beta, so the sum would sit in front of the whole sweep.)  The state
+// sits in two slots: A reads slot 0, B reads slot 0 and block 0 writes the
+// updated state to slot 1, F writes slot 0 from slot 1, so no block reads
+// what its own launch writes.  Every kernel returns at once when the solve
+// has finished (still handing the state on), so the host enqueues whole
+// chunks of iterations and looks at the state only between chunks (one
+// chunk ahead).  A chunk ends with a fold (x += pending alpha p [+ x_lo])
+// and an FP64 true-residual sweep: always in the mixed solver (the reliable
+// update), only after an iterated convergence in the FP64 solver.  The
+// preconditioned solver keeps the one-block finalize after phase A as well
+// (its preconditioner's 2n sweeps dwarf it).
 #include <algorithm>
 #include <cmath>
 #include <cstdlib>
@@ -23,9 +34,11 @@ namespace hub {
 
 Link16 make_link16(const Geom& g, const void* links);
 
-__global__ void k_zero_scalars(CGScalars* sc) {
+// Zero `count` consecutive scalar slots.
+__global__ void k_zero_scalars(CGScalars* sc, int count) {
     uint32_t* w = reinterpret_cast<uint32_t*>(sc);
-    for (int k = threadIdx.x; k < (int)(sizeof(CGScalars) / 4); k += blockDim.x) w[k] = 0;
+    for (int k = threadIdx.x; k < count * (int)(sizeof(CGScalars) / 4); k += blockDim.x)
+        w[k] = 0;
 }
 
 // r = phi, p = 0, x = 0 (x_lo = 0), |phi|^2 (deposits; k_init_finish).
@@ -58,12 +71,86 @@ __global__ __launch_bounds__(256) void k_phaseB(const CGScalars* sc, Vec* __rest
     deposit<256, 1>(part, partials, blockIdx.x);
 }
 
+// Phase B with the phase-A reduction taken in: every block adds the n_pq
+// p.q deposits (the order of reduce_deposits<256, 1>), sets alpha = rho/p.q,
+// then r -= alpha q and r.r deposits.  Block 0 writes the state to sc_out.
+template <class Vec>
+__global__ __launch_bounds__(256) void k_phaseB_fused(const CGScalars* __restrict__ sc_in,
+                                                      CGScalars* __restrict__ sc_out,
+                                                      const double* __restrict__ dep_pq,
+                                                      int n_pq, Vec* __restrict__ r,
+                                                      const Vec* __restrict__ q, int V,
+                                                      double* dep_rr) {
+    if (sc_in->done != kRunning) {
+        if (blockIdx.x == 0 && threadIdx.x == 0) *sc_out = *sc_in;
+        return;
+    }
+    // The loads of r and q do not depend on alpha: issue them before the
+    // reduction (a barrier does not wait for outstanding global loads).
+    const int base = lane_base(blockIdx.x), cnt = lane_count(base, V);
+    Vec rv[8], qv[8];
+    if (cnt == 8) {
+        ld8(r + base, rv);
+        ld8(q + base, qv);
+    } else {
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+            rv[k] = k < cnt ? r[base + k] : (Vec)0;
+            qv[k] = k < cnt ? q[base + k] : (Vec)0;
+        }
+    }
+    const double pq = reduce_deposits_canon(dep_pq, n_pq);
+    CGScalars s = *sc_in;
+    s.pq = pq;
+    s.gamma = 1.0;
+    if (!(pq > 0.0) || !isfinite(pq)) {
+        s.done = kDoneBreakdown;
+        s.alpha = 0.0;  // alpha_prev was applied by phase A
+    } else {
+        s.alpha = s.rho / pq;
+    }
+    if (blockIdx.x == 0 && threadIdx.x == 0) *sc_out = s;
+    if (s.done != kRunning) return;
+    const Vec alpha = (Vec)s.alpha;
+    double part[1] = {0.0};
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+        rv[k] = rv[k] - alpha * qv[k];
+        part[0] += (double)rv[k] * (double)rv[k];
+    }
+    if (cnt == 8) {
+        st8(r + base, rv);
+    } else {
+#pragma unroll
+        for (int k = 0; k < 8; ++k)
+            if (k < cnt) r[base + k] = rv[k];
+    }
+    deposit<256, 1>(part, dep_rr, blockIdx.x);
+}
+
 __global__ __launch_bounds__(256) void k_phaseB_finish(CGScalars* sc, const double* partials,
                                                        int n) {
     if (sc->done != kRunning) return;
     double tot[1];
     reduce_deposits<256, 1>(partials, n, tot);
     if (threadIdx.x == 0) finish_phaseB(sc, tot[0]);
+}
+
+// As k_phaseB_finish, reading the state from sc_in and writing it to sc_out.
+__global__ __launch_bounds__(256) void k_phaseB_finish_to(const CGScalars* __restrict__ sc_in,
+                                                          CGScalars* __restrict__ sc_out,
+                                                          const double* partials, int n) {
+    if (sc_in->done != kRunning) {
+        if (threadIdx.x == 0) *sc_out = *sc_in;
+        return;
+    }
+    double tot[1];
+    reduce_deposits<256, 1>(partials, n, tot);
+    if (threadIdx.x == 0) {
+        CGScalars s = *sc_in;
+        finish_phaseB(&s, tot[0]);
+        *sc_out = s;
+    }
 }
 
 __global__ __launch_bounds__(256) void k_pcg_phaseB_finish(CGScalars* sc,
@@ -138,8 +225,9 @@ struct Solver {
     hipStream_t st;
     SweepPlan P;
     // device buffers
-    CGScalars* sc;
-    double* partials;
+    CGScalars* sc;     // slot 0 (slot 1 follows it)
+    double* partials;  // phase A / residual / preconditioner deposits
+    double* dep_rr;    // phase B deposits (fused iterations)
     const double* phi;
     double* x;
     const double* A64;
@@ -174,6 +262,19 @@ struct Solver {
         const bool pcg = !cheb.empty();
         if constexpr (sizeof(Vec) == 8) {
             if (pcg) opA.r = z;  // p_new = z + beta p_old
+        }
+        if (!pcg) {
+            // A reads slot 0; B reads slot 0 and writes slot 1; F writes slot 0.
+            const int ne = elem_tiles(g.V);
+            for (int k = 0; k < iters; ++k) {
+                HUB_TRY(launch_q(g, P, opA, (Vec*)yscratch, partials, st, false));
+                k_phaseB_fused<Vec><<<ne, 256, 0, st>>>(sc, sc + 1, partials, P.ntiles, r, q,
+                                                        g.V, dep_rr);
+                k_phaseB_finish_to<<<1, 256, 0, st>>>(sc + 1, sc, dep_rr, ne);
+            }
+            HUB_TRY(fold_and_residual(mixed ? kModeReliable : kModeCheck));
+            HUB_HIP(hipMemcpyAsync(snap, sc, sizeof(CGScalars), hipMemcpyDeviceToHost, st));
+            return HUB_OK;
         }
         for (int k = 0; k < iters; ++k) {
             if constexpr (sizeof(Vec) == 8) {
@@ -244,7 +345,7 @@ hub_status run_solver(Solver<Vec, Lnk>& S, bool mixed, hub_cg_stats* out) {
     S.st = H.stream;
     hipStream_t st = S.st;
     HUB_HIP(hipEventRecord(H.t0, st));
-    k_zero_scalars<<<1, 64, 0, st>>>(S.sc);
+    k_zero_scalars<<<1, 64, 0, st>>>(S.sc, 2);
     k_init<Vec><<<elem_tiles(g.V), 256, 0, st>>>(S.phi, S.r, S.p0, S.x, S.xlo, g.V, S.partials);
     k_init_finish<<<1, 256, 0, st>>>(S.sc, S.partials, elem_tiles(g.V), o.tol * o.tol,
                                      mixed ? kReliableDelta * kReliableDelta : 0.0, o.max_iter);
@@ -326,8 +427,9 @@ hub_status solve(const Geom& g, const double* sigma, const double* phi, double* 
     const SweepPlan P = plan_sweep(g, !mixed);
     auto al = [](size_t b) { return (b + 255) & ~size_t(255); };
     size_t off = 0;
-    const size_t o_sc = off; off += al(sizeof(CGScalars));
+    const size_t o_sc = off; off += al(2 * sizeof(CGScalars));
     const size_t o_part = off; off += al(sizeof(double) * max_partials(g));
+    const size_t o_rr = off; off += al(sizeof(double) * elem_tiles(g.V));
     const size_t o_A64 = off; off += al(8 * V);
     const size_t o_lnk = off; off += mixed ? al(dtype_size(o.link) * V) : 0;
     const size_t o_r = off; off += al(vb * V);
@@ -352,6 +454,7 @@ hub_status solve(const Geom& g, const double* sigma, const double* phi, double* 
             Solver<double, Link64> S{g, o, st, P};
             S.sc = (CGScalars*)(ws + o_sc);
             S.partials = (double*)(ws + o_part);
+            S.dep_rr = (double*)(ws + o_rr);
             S.phi = phi;
             S.x = x;
             S.A64 = A64;
@@ -373,6 +476,7 @@ hub_status solve(const Geom& g, const double* sigma, const double* phi, double* 
             Solver<float, Link32> S{g, o, st, P};
             S.sc = (CGScalars*)(ws + o_sc);
             S.partials = (double*)(ws + o_part);
+            S.dep_rr = (double*)(ws + o_rr);
             S.phi = phi;
             S.x = x;
             S.A64 = A64;
@@ -388,6 +492,7 @@ hub_status solve(const Geom& g, const double* sigma, const double* phi, double* 
             Solver<float, Link16> S{g, o, st, P};
             S.sc = (CGScalars*)(ws + o_sc);
             S.partials = (double*)(ws + o_part);
+            S.dep_rr = (double*)(ws + o_rr);
             S.phi = phi;
             S.x = x;
             S.A64 = A64;
@@ -434,7 +539,7 @@ double reliable_delta() { return kReliableDelta; }
 hub_status serve_slot_init(const Geom& g, CGScalars* sc, const double* phi, float* r, float* p0,
                            double* x, float* xlo, double tol2, double delta2, int max_iter,
                            double* partials, hipStream_t st) {
-    k_zero_scalars<<<1, 64, 0, st>>>(sc);
+    k_zero_scalars<<<1, 64, 0, st>>>(sc, 1);
     k_init<float><<<elem_tiles(g.V), 256, 0, st>>>(phi, r, p0, x, xlo, g.V, partials);
     k_init_finish<<<1, 256, 0, st>>>(sc, partials, elem_tiles(g.V), tol2, delta2, max_iter);
     HUB_HIP(hipGetLastError());

@@ -132,6 +132,42 @@ __device__ inline void reduce_deposits(const double* partials, int n, double (&t
     }
 }
 
+// The sum of n single-value deposits in exactly the order of
+// reduce_deposits<256, 1> (so with the same bits), computed by a block of
+// any multiple of 64 lanes: its waves take the four 64-lane groups of a
+// 256-lane block in turn.  Result in every thread.  Lets a kernel of any
+// block size reduce the previous kernel's deposits itself and get what a
+// one-block finalize would.
+__device__ inline double reduce_deposits_canon(const double* partials, int n) {
+    constexpr int B = 256;
+    __shared__ double red[4];
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    const int nw = (int)(blockDim.x >> 6);
+    __syncthreads();  // red[] may still be read by a previous call
+    for (int vw = wid; vw < 4; vw += nw) {
+        double s = 0.0;
+        int b = vw * 64 + lane;
+        for (; b + 3 * B < n; b += 4 * B) {
+            const double v0 = partials[b];
+            const double v1 = partials[b + B];
+            const double v2 = partials[b + 2 * B];
+            const double v3 = partials[b + 3 * B];
+            s += v0;
+            s += v1;
+            s += v2;
+            s += v3;
+        }
+        for (; b < n; b += B) s += partials[b];
+        s = wave_sum(s);
+        if (lane == 0) red[vw] = s;
+    }
+    __syncthreads();
+    double tot = 0.0;
+#pragma unroll
+    for (int w = 0; w < 4; ++w) tot += red[w];
+    return tot;
+}
+
 // Largest number of sums any reduction deposits per tile.
 constexpr int kMaxNP = 2;
 

@@ -155,13 +155,13 @@ __device__ OpPhaseA<float, float, float, Lnk> slot_phaseA(const SlotDesc& S) {
     op.q = S.q;
     op.x = S.xlo;
     op.lk = slot_link<Lnk>(S);
-    op.begin();
+    (void)op.begin();
     return op;
 }
 
 __device__ OpResidual<float> slot_residual(const SlotDesc& S) {
     OpResidual<float> op{S.sc, S.x, S.phi, S.r, S.p0, S.p1, Link64{S.A64}, kModeReliable};
-    op.begin();
+    (void)op.begin();
     return op;
 }
 

@@ -122,7 +122,7 @@ struct OpApply {
     Vec* z;
     Lnk lk;
     __device__ bool skip() const { return false; }
-    __device__ void begin() {}
+    __device__ bool begin() { return true; }
     __device__ Vec load_h(int i) const { return x[i]; }
     __device__ Acc val_h(Vec r) const { return (Acc)r; }
     __device__ Vec load_c(int i) const { return x[i]; }
@@ -149,6 +149,8 @@ struct OpApply {
 //   partial p_new . q  (FP64 accumulation); gamma = 1 except right after a
 //   reliable update, where it removes the component of p along the new r.
 // p is double-buffered by iteration parity so halo reads never see a p_new.
+// The p.q deposits are added either by a one-block finalize (finish(), which
+// sets alpha) or by the next kernel's blocks themselves.
 template <class Acc, class Vec, class XVec, class Lnk>
 struct OpPhaseA {
     using acc_t = Acc;
@@ -178,13 +180,14 @@ struct OpPhaseA {
     Vec* pnew;
     Acc beta, alpha, gamma;
     __device__ bool skip() const { return sc->done != kRunning; }
-    __device__ void begin() {
+    __device__ bool begin() {
         const int it = sc->iter;
         pold = (it & 1) ? pbuf1 : pbuf0;
         pnew = (it & 1) ? pbuf0 : pbuf1;
         beta = (Acc)sc->beta;
         alpha = (Acc)sc->alpha;
         gamma = (Acc)sc->gamma;
+        return true;
     }
     __device__ raw_t load_h(int i) const { return {r[i], pold[i]}; }
     __device__ Acc val_h(const raw_t& v) const { return gamma * (Acc)v.r + beta * (Acc)v.p; }
@@ -267,7 +270,10 @@ struct OpResidual {
     int mode;
     const RVec* pcur;  // set by begin()
     __device__ bool skip() const { return !mode_runs(mode, sc->done); }
-    __device__ void begin() { pcur = (sc->iter & 1) ? pbuf1 : pbuf0; }
+    __device__ bool begin() {
+        pcur = (sc->iter & 1) ? pbuf1 : pbuf0;
+        return true;
+    }
     __device__ double load_h(int i) const { return x[i]; }
     __device__ double val_h(double v) const { return v; }
     __device__ craw_t load_c(int i) const { return {x[i], phi[i], pcur[i]}; }
@@ -347,7 +353,7 @@ struct OpChebW {
     double* w;
     Link64 lk;
     __device__ bool skip() const { return sc && sc->done != kRunning; }
-    __device__ void begin() {}
+    __device__ bool begin() { return true; }
     __device__ double load_h(int i) const { return v[i]; }
     __device__ double val_h(double r) const { return r; }
     __device__ double load_c(int i) const { return v[i]; }
@@ -389,7 +395,7 @@ struct OpChebZ {
     double c2, c1, c0;
     Link64 lk;
     __device__ bool skip() const { return sc && sc->done != kRunning; }
-    __device__ void begin() {}
+    __device__ bool begin() { return true; }
     __device__ double load_h(int i) const { return w[i]; }
     __device__ double val_h(double x) const { return x; }
     __device__ craw_t load_c(int i) const { return {w[i], v[i], kDot ? r[i] : 0.0}; }
@@ -570,7 +576,7 @@ template <class Op, int TX, int TT>
 __global__ __launch_bounds__(TX) void k_mtm_d1(Geom g, Op op, int tiles_x, int ntiles,
                                                double* partials) {
     if (op.skip()) return;
-    op.begin();
+    if (!op.begin()) return;
     const int b = xcd_remap(blockIdx.x, gridDim.x);
     double part[Op::kNP] = {};
     if (b < ntiles) tile_mtm_d1<Op, TX, TT>(g, op, tiles_x, b, nullptr, part);
@@ -691,7 +697,7 @@ template <class Op, int TX, int TT>
 __global__ __launch_bounds__(TX / 2) void k_mtm_d1p(Geom g, Op op, int tiles_x, int ntiles,
                                                     double* partials) {
     if (op.skip()) return;
-    op.begin();
+    if (!op.begin()) return;
     const int b = xcd_remap(blockIdx.x, gridDim.x);
     double part[Op::kNP] = {};
     if (b < ntiles) tile_mtm_d1p<Op, TX, TT>(g, op, tiles_x, b, part);
@@ -930,7 +936,7 @@ __global__ __launch_bounds__(BLOCK) void k_mtm_d3(Geom g, Op op, int tiles_y, in
     using Acc = typename Op::acc_t;
     __shared__ Acc lds[d3_lds_elems<NX, TY, TZ>()];
     if (op.skip()) return;
-    op.begin();
+    if (!op.begin()) return;
     const int b = xcd_remap(blockIdx.x, gridDim.x);
     double part[Op::kNP] = {};
     tile_mtm_d3<Op, NX, TY, TZ, BLOCK>(g, op, tiles_y, tiles_z, tc, b, lds, part);
@@ -961,7 +967,7 @@ __device__ inline typename Op::acc_t gen_M_at(const Geom& g, const Op& op, int i
 template <class Op>
 __global__ __launch_bounds__(256) void k_gen_pass1(Geom g, Op op, typename Op::acc_t* y) {
     if (op.skip()) return;
-    op.begin();
+    if (!op.begin()) return;
     const int i = blockIdx.x * 256 + threadIdx.x;
     if (i < g.V) y[i] = gen_M_at(g, op, i);
 }
@@ -972,7 +978,7 @@ __global__ __launch_bounds__(256) void k_gen_pass2(Geom g, Op op,
                                                    double* partials) {
     using Acc = typename Op::acc_t;
     if (op.skip()) return;
-    op.begin();
+    if (!op.begin()) return;
     const int i = blockIdx.x * 256 + threadIdx.x;
     double part[Op::kNP] = {};
     if (i < g.V) {

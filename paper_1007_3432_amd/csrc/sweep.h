@@ -190,10 +190,13 @@ inline int max_partials(const Geom& g) {
 }
 
 // One sweep: z = Q in, consumed by op.out().  y: scratch of g.V acc_t
-// elements, used by the generic path only.
+// elements, used by the generic path only.  A reducing op's deposits go to
+// partials; with finalize, a one-block kernel then adds them (op.finish),
+// otherwise the next kernel does.
 template <class Op>
 hub_status launch_q(const Geom& g, const SweepPlan& P, const Op& op,
-                    typename Op::acc_t* y, double* partials, hipStream_t st) {
+                    typename Op::acc_t* y, double* partials, hipStream_t st,
+                    bool finalize = true) {
     if (P.kind == kSweepD1 && P.pair) {
         if constexpr (op_has_pair<Op>::value) {
             switch (P.variant) {
@@ -270,7 +273,7 @@ hub_status launch_q(const Geom& g, const SweepPlan& P, const Op& op,
     }
     if constexpr (Op::kReduce) {
         if (!partials) return set_error(HUB_E_INVALID, "internal: reduction needs deposits");
-        k_finish_op<Op><<<1, 256, 0, st>>>(op, partials, P.ntiles);
+        if (finalize) k_finish_op<Op><<<1, 256, 0, st>>>(op, partials, P.ntiles);
     }
     HUB_HIP(hipGetLastError());
     return HUB_OK;
