@@ -194,6 +194,32 @@ def test_logdet_no_hopping():
     assert sign == 1.0 and logdet == pytest.approx(expect, abs=1e-13)
 
 
+@pytest.mark.parametrize("d,nx,mu", [(1, 6, 0.0), (1, 5, 0.3), (2, 3, -0.2)])
+def test_trotter_limit_free_fermions(d, nx, mu):
+    """U = 0: as dtau -> 0 at fixed beta = nt dtau, det M tends to
+    det(1 + exp(-beta (K - mu))), the one-spin factor of the free grand
+    partition function Tr exp(-beta (H - mu N)) of Eq. (4); the stencil form
+    is first order in dtau, so the error halves when nt doubles.  K is built
+    from Eq. (9) independently of the oracle."""
+    beta = 2.0
+    K = dense.kinetic_matrix(d, nx, 1.0)
+    ev = np.linalg.eigvalsh(K)
+    exact = float(np.sum(np.log1p(np.exp(-beta * (ev - mu)))))
+    logdets = []
+    for nt in (8, 16, 32, 64):
+        lat = Lattice(d, nx, nt, 1.0, beta / nt, 0.0, mu)
+        sigma, _ = inputs.sigma_eta(d, nx, nt, seed=nt)
+        A = oracle.links(lat, sigma)
+        sign, logdet = np.linalg.slogdet(_dense_M(lat, A))
+        assert sign == 1.0
+        logdets.append(logdet)
+    errs = [l - exact for l in logdets]
+    for a, b in zip(errs, errs[1:]):
+        assert 0.45 <= b / a <= 0.6, errs   # first order, same sign
+    # Richardson extrapolation of the first-order error lands on the limit
+    assert abs(2 * logdets[-1] - logdets[-2] - exact) <= 5e-3 * abs(exact)
+
+
 def test_free_fermions_U0():
     """U = 0: b = 0, every link factor equals exp(dtau mu) whatever sigma."""
     lat = Lattice(3, 3, 4, 1.0, 0.05, 0.0, 0.4)
