@@ -31,6 +31,11 @@ __device__ __forceinline__ D2 ld2(const double* p) {
 __device__ __forceinline__ void st2(double* p, double a, double b) {
     *reinterpret_cast<double2*>(p) = make_double2(a, b);
 }
+typedef double d2_vec __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ void st2_nt(double* p, double a, double b) {
+    const d2_vec v = {a, b};
+    __builtin_nontemporal_store(v, reinterpret_cast<d2_vec*>(p));
+}
 
 // Every link reader splits the access into the load (raw) and the value
 // (val), so that a sweep can issue the loads of a later slice early and form
@@ -129,18 +134,22 @@ struct OpApply {
     __device__ Acc val_c(Vec r, NoCenter&) const { return (Acc)r; }
     __device__ lraw_t lraw(int i) const { return lk.raw(i); }
     __device__ Acc lval(lraw_t r, int s) const { return (Acc)lk.val(r, s); }
+    // The result is not read again by this sweep: stream it past the caches
+    // (non-temporal stores), so that it does not wait in L2 for the
+    // write-back at the end of the kernel.
     __device__ void out(int i, Acc zv, Acc, const NoCenter&, double (&)[kNP]) const {
-        z[i] = (Vec)zv;
+        __builtin_nontemporal_store((Vec)zv, z + i);
     }
     __device__ void finish(const double (&)[kNP]) const {}
     static constexpr bool kPair = sizeof(Acc) == 8 && sizeof(Vec) == 8 &&
                                   std::is_same<Lnk, Link64>::value;
+    static constexpr bool kMarch = kPair;
     __device__ D2 in2(int i) const { return ld2((const double*)x + i); }
     __device__ D2 in_center2(int i, NoCenter&, NoCenter&) const { return in2(i); }
     __device__ D2 link2(int i, int s) const { return lk.pair(i, s); }
     __device__ void out2(int i, D2 zv, D2, const NoCenter&, const NoCenter&,
                          double (&)[kNP]) const {
-        st2((double*)z + i, zv.a, zv.b);
+        st2_nt((double*)z + i, zv.a, zv.b);
     }
 };
 
@@ -472,10 +481,28 @@ __global__ __launch_bounds__(256) void k_finish_op(Op op, const double* partials
 template <int TX, int TT>
 constexpr int d1_lds_elems() { return 0; }
 
+// Moves by one lane across the 64-wide wavefront as DPP wavefront shifts
+// (wave_shr:1 / wave_shl:1, a register move per 32 bits, no LDS round trip).
+// The lane without a source (lane 0 up, lane 63 down) keeps its own value.
+template <int CTRL, class T>
+__device__ __forceinline__ T dpp_wave_shift(T v) {
+    static_assert(sizeof(T) == 4 || sizeof(T) == 8, "32- or 64-bit values");
+    if constexpr (sizeof(T) == 4) {
+        const int w = __builtin_bit_cast(int, v);
+        return __builtin_bit_cast(T, __builtin_amdgcn_update_dpp(w, w, CTRL, 0xf, 0xf, false));
+    } else {
+        const long long w = __builtin_bit_cast(long long, v);
+        const int lo = (int)w, hi = (int)(w >> 32);
+        const int rlo = __builtin_amdgcn_update_dpp(lo, lo, CTRL, 0xf, 0xf, false);
+        const int rhi = __builtin_amdgcn_update_dpp(hi, hi, CTRL, 0xf, 0xf, false);
+        return __builtin_bit_cast(T, (long long)(((unsigned long long)(unsigned)rhi << 32) |
+                                                 (unsigned)rlo));
+    }
+}
 template <class T>
-__device__ __forceinline__ T lane_up(T v) { return __shfl_up(v, 1, 64); }    // from lane-1
+__device__ __forceinline__ T lane_up(T v) { return dpp_wave_shift<0x138>(v); }    // from lane-1
 template <class T>
-__device__ __forceinline__ T lane_down(T v) { return __shfl_down(v, 1, 64); }  // from lane+1
+__device__ __forceinline__ T lane_down(T v) { return dpp_wave_shift<0x130>(v); }  // from lane+1
 
 // One tile b of the sweep (block of >= TX lanes, TX a multiple of 64); adds
 // this lane's share of the op's sums to part.
@@ -703,6 +730,117 @@ __global__ __launch_bounds__(TX / 2) void k_mtm_d1p(Geom g, Op op, int tiles_x, 
     if (b < ntiles) tile_mtm_d1p<Op, TX, TT>(g, op, tiles_x, b, part);
     if constexpr (Op::kReduce) deposit<TX / 2, Op::kNP>(part, partials, b);
 }
+
+// ---------------------------------------------------------------------------
+// Marching variant of the pair sweep (the bare FP64 product, d = 1, nx even).
+//
+// Each wavefront owns 128 x-sites, as in tile_mtm_d1p, but covers TS
+// consecutive slices, taking them in "stages": stage j holds the input row
+// of slice s0-1+j (j = 0 .. h+1) and the A row of the same slice (j >= 1).
+// Stage j gives y on slice s0-1+j and, from stage 2 on, z on slice s0+j-2;
+// the loads of stage j+PF are issued before stage j is consumed.  Over TS
+// slices a wavefront reads TS+2 input rows and TS+1 A rows through L1
+// instead of 2 and 1.5 per slice for the two-slice tile, and its stores
+// overlap the loads of later stages.
+template <class Op, int TX, int TS, int PF>
+__device__ __forceinline__ void tile_mtm_d1m(const Geom& g, const Op& op, int tiles_x, int b,
+                                             double (&part)[Op::kNP]) {
+    static_assert(TX % 128 == 0, "tile width is whole pair wavefronts");
+    using Center = typename Op::center_t;
+    const int nx = g.nx, nt = g.nt;
+    const int tx = b % tiles_x, tt = b / tiles_x;
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    if (wave >= TX / 128) return;
+    const int n0 = tx * TX + 128 * wave;
+    const int w = min(128, nx - n0);
+    if (w <= 0) return;
+    const int np = w >> 1;
+    const int s0 = tt * TS, h = min(TS, nt - s0);
+    const double kappa = g.kappa;
+    const bool own = lane < np;
+    const int site = n0 + 2 * (own ? lane : np - 1);
+    const bool solo = np == 1;
+    const bool left = lane == 0, right = lane == (solo ? 1 : np - 1);
+    const bool edge = left || right;
+    const int h1 = wrap1(left ? n0 - 1 : n0 + w, nx);
+    const int h2 = wrap1(left ? n0 - 2 : n0 + w + 1, nx);
+
+    D2 xv[TS + 2], av[TS + 2];
+    double x1[TS + 2], x2[TS + 2], a1[TS + 2];
+    Center cen[TS + 2][2];
+    auto load = [&](int j) {
+        const int sl = wrap1(s0 - 1 + j, nt);
+        const int row = sl * nx;
+        if (j >= 1 && j <= h)
+            xv[j] = op.in_center2(row + site, cen[j][0], cen[j][1]);
+        else
+            xv[j] = op.in2(row + site);
+        if (j >= 1) av[j] = op.link2(row + site, sl);
+        if (edge) {
+            x1[j] = op_in(op, row + h1);
+            x2[j] = op_in(op, row + h2);
+            if (j >= 1) a1[j] = op_link(op, row + h1, sl);
+        }
+    };
+#pragma unroll
+    for (int j = 0; j < PF && j < TS + 2; ++j)
+        if (j <= h + 1) load(j);
+    D2 y_prev{0.0, 0.0};
+    double yh_prev = 0.0;
+#pragma unroll
+    for (int j = 0; j < TS + 2; ++j) {
+        if (j + PF < TS + 2 && j + PF <= h + 1) load(j + PF);
+        if (j == 0 || j > h + 1) continue;
+        const D2 xc = xv[j];
+        double xm = lane_up(xc.b), xp = lane_down(xc.a);
+        if (left) xm = x1[j];
+        if (right) xp = x1[j];
+        if (solo) {
+            const double xr = lane_down(x1[j]);
+            if (left) xp = xr;
+        }
+        D2 y;
+        y.a = xc.a - kappa * (xm + xc.b) + av[j].a * xv[j - 1].a;
+        y.b = xc.b - kappa * (xc.a + xp) + av[j].b * xv[j - 1].b;
+        double yh = 0.0;
+        if (edge) yh = x1[j] - kappa * (x2[j] + (left ? xc.a : xc.b)) + a1[j] * x1[j - 1];
+        if (j >= 2) {
+            double ym = lane_up(y_prev.b), yp = lane_down(y_prev.a);
+            if (left) ym = yh_prev;
+            if (right) yp = yh_prev;
+            if (solo) {
+                const double yr = lane_down(yh_prev);
+                if (left) yp = yr;
+            }
+            D2 zv;
+            zv.a = y_prev.a - kappa * (ym + y_prev.b) + av[j].a * y.a;
+            zv.b = y_prev.b - kappa * (y_prev.a + yp) + av[j].b * y.b;
+            if (own)
+                op.out2((s0 + j - 2) * nx + site, zv, xv[j - 1], cen[j - 1][0], cen[j - 1][1],
+                        part);
+        }
+        y_prev = y;
+        yh_prev = yh;
+    }
+}
+
+template <class Op, int TX, int TS, int PF>
+__global__ __launch_bounds__(TX / 2) void k_mtm_d1m(Geom g, Op op, int tiles_x, int ntiles,
+                                                    double* partials) {
+    if (op.skip()) return;
+    if (!op.begin()) return;
+    const int b = xcd_remap(blockIdx.x, gridDim.x);
+    double part[Op::kNP] = {};
+    if (b < ntiles) tile_mtm_d1m<Op, TX, TS, PF>(g, op, tiles_x, b, part);
+    if constexpr (Op::kReduce) deposit<TX / 2, Op::kNP>(part, partials, b);
+}
+
+// Whether an op takes the marching d = 1 tile (kMarch, default false): ops
+// whose output is not read again soon (the bare product).
+template <class Op, class = void>
+struct op_marches : std::false_type {};
+template <class Op>
+struct op_marches<Op, std::void_t<decltype(Op::kMarch)>> : std::bool_constant<Op::kMarch> {};
 
 // ---------------------------------------------------------------------------
 // Fused Q = M^T M sweep for d = 3, nx = NX.

@@ -198,6 +198,32 @@ hub_status launch_q(const Geom& g, const SweepPlan& P, const Op& op,
                     typename Op::acc_t* y, double* partials, hipStream_t st,
                     bool finalize = true) {
     if (P.kind == kSweepD1 && P.pair) {
+        if constexpr (op_marches<Op>::value) {
+            // The bare product takes the marching tile (8 slices per
+            // wavefront, all but the last stage's loads issued up front)
+            // unless a pair tile is forced for tuning.
+            if (d1p_tile_override() < 0) {
+                constexpr int kTS = 8, kPF = 8;
+                const int tx = kD1PShapes[P.variant].tx;
+                const int ntiles = P.tiles_x * ceil_div(g.nt, kTS);
+                switch (tx) {
+                    case 512:
+                        k_mtm_d1m<Op, 512, kTS, kPF><<<ntiles, 256, 0, st>>>(g, op, P.tiles_x,
+                                                                             ntiles, partials);
+                        break;
+                    case 256:
+                        k_mtm_d1m<Op, 256, kTS, kPF><<<ntiles, 128, 0, st>>>(g, op, P.tiles_x,
+                                                                             ntiles, partials);
+                        break;
+                    default:
+                        k_mtm_d1m<Op, 128, kTS, kPF><<<ntiles, 64, 0, st>>>(g, op, P.tiles_x,
+                                                                            ntiles, partials);
+                        break;
+                }
+                HUB_HIP(hipGetLastError());
+                return HUB_OK;
+            }
+        }
         if constexpr (op_has_pair<Op>::value) {
             switch (P.variant) {
 #define HUB_D1P_CASE(K, TX, TT)                                                         \
