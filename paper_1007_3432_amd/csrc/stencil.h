@@ -874,11 +874,12 @@ constexpr int d3_lds_elems() {
 
 // One tile b of the sweep (block of BLOCK lanes); adds this lane's share of
 // the op's sums to part.  lds: d3_lds_elems<NX, TY, TZ>() elements.
-template <class Op, int NX, int TY, int TZ, int BLOCK>
+template <class Op, int NX, int TY, int TZ, int BLOCK, int PD = 1>
 __device__ __forceinline__ void tile_mtm_d3(const Geom& g, const Op& op, int tiles_y,
                                             int tiles_z, int tc, int b,
                                             typename Op::acc_t* lds,
                                             double (&part)[Op::kNP]) {
+    static_assert(PD == 1 || PD == 2, "prefetch depth 1 or 2 slices");
     using Acc = typename Op::acc_t;
     using Center = typename Op::center_t;
     using Raw = typename Op::raw_t;
@@ -972,39 +973,43 @@ __device__ __forceinline__ void tile_mtm_d3(const Geom& g, const Op& op, int til
                                X[j - NX * XY] + X[j + NX * XY]);
     };
 
-    // Loads of one slice, issued a step before they are used.
-    CRaw pc[NC];
-    LRaw pa[NC];
-    Raw ph[NHX];
-    LRaw pah[NHY];
-    auto prefetch = [&](int sl) {
+    // Loads of one slice, issued PD steps before they are used (PD = 2: two
+    // buffers, alternating by step parity).
+    struct Pre {
+        CRaw pc[NC];
+        LRaw pa[NC];
+        Raw ph[NHX];
+        LRaw pah[NHY];
+    };
+    Pre pre0, pre1;
+    auto prefetch = [&](Pre& P, int sl) {
         const int off = vs * sl;
 #pragma unroll
         for (int k = 0; k < NC; ++k) {
-            pc[k] = op.load_c(cn[k] + off);
-            pa[k] = op.lraw(cn[k] + off);
+            P.pc[k] = op.load_c(cn[k] + off);
+            P.pa[k] = op.lraw(cn[k] + off);
         }
 #pragma unroll
-        for (int k = 0; k < NHX; ++k) ph[k] = op.load_h(hxs[k] + off);
+        for (int k = 0; k < NHX; ++k) P.ph[k] = op.load_h(hxs[k] + off);
 #pragma unroll
-        for (int k = 0; k < NHY; ++k) pah[k] = op.lraw(hys[k] + off);
+        for (int k = 0; k < NHY; ++k) P.pah[k] = op.lraw(hys[k] + off);
     };
     // x_s, x_{s+1} and op state at the owned sites; x_s at the Y-halo
     // positions; A_{s+1} at both.
     Acc xs_c[NC], xn_c[NC], an_c[NC], xs_h[NHY], an_h[NHY];
     Center cs_c[NC], cn_c[NC];
     // The prefetched slice sl into X, xn_c / cn_c and an_c / an_h.
-    auto stage = [&](int sl) {
+    auto stage = [&](const Pre& P, int sl) {
 #pragma unroll
         for (int k = 0; k < NC; ++k) {
-            xn_c[k] = op.val_c(pc[k], cn_c[k]);
-            an_c[k] = op.lval(pa[k], sl);
+            xn_c[k] = op.val_c(P.pc[k], cn_c[k]);
+            an_c[k] = op.lval(P.pa[k], sl);
             X[cxi[k]] = xn_c[k];
         }
 #pragma unroll
-        for (int k = 0; k < NHX; ++k) X[hxi[k]] = op.val_h(ph[k]);
+        for (int k = 0; k < NHX; ++k) X[hxi[k]] = op.val_h(P.ph[k]);
 #pragma unroll
-        for (int k = 0; k < NHY; ++k) an_h[k] = op.lval(pah[k], sl);
+        for (int k = 0; k < NHY; ++k) an_h[k] = op.lval(P.pah[k], sl);
     };
 
     // Prologue: x_{s0-1} at the owned and Y-halo positions, slice s0 into X,
@@ -1015,9 +1020,10 @@ __device__ __forceinline__ void tile_mtm_d3(const Geom& g, const Op& op, int til
         for (int k = 0; k < NC; ++k) xs_c[k] = op_in(op, cn[k] + offm);
 #pragma unroll
         for (int k = 0; k < NHY; ++k) xs_h[k] = op_in(op, hys[k] + offm);
-        prefetch(s0);
-        stage(s0);
-        prefetch(wrap1(s0 + 1, nt));
+        prefetch(pre0, s0);
+        stage(pre0, s0);
+        prefetch(pre0, wrap1(s0 + 1, nt));
+        if (PD == 2 && h > 1) prefetch(pre1, wrap1(s0 + 2, nt));
         __syncthreads();
 #pragma unroll
         for (int k = 0; k < NC; ++k) Y[cyi[k]] = wx(cx[k], cxi[k]) + an_c[k] * xs_c[k];
@@ -1034,10 +1040,12 @@ __device__ __forceinline__ void tile_mtm_d3(const Geom& g, const Op& op, int til
         __syncthreads();
     }
 
-    for (int r = 0; r < h; ++r) {
+    // Step r emits z on slice s0 + r; the slice it stages was loaded PD
+    // steps earlier into the buffer of parity r (PD = 2) or the one buffer.
+    auto step = [&](int r, Pre& P) {
         const int s = s0 + r;
-        stage(wrap1(s + 1, nt));
-        if (r + 1 < h) prefetch(wrap1(s + 2, nt));
+        stage(P, wrap1(s + 1, nt));
+        if (r + PD < h) prefetch(P, wrap1(s + 1 + PD, nt));
         __syncthreads();
         Acc yo[NC], yh[NHY];
 #pragma unroll
@@ -1065,10 +1073,18 @@ __device__ __forceinline__ void tile_mtm_d3(const Geom& g, const Op& op, int til
         }
 #pragma unroll
         for (int k = 0; k < NHY; ++k) Y[hyi[k]] = yh[k];
+    };
+    if constexpr (PD == 1) {
+        for (int r = 0; r < h; ++r) step(r, pre0);
+    } else {
+        for (int r = 0; r < h; r += 2) {
+            step(r, pre0);
+            if (r + 1 < h) step(r + 1, pre1);
+        }
     }
 }
 
-template <class Op, int NX, int TY, int TZ, int BLOCK>
+template <class Op, int NX, int TY, int TZ, int BLOCK, int PD = 1>
 __global__ __launch_bounds__(BLOCK) void k_mtm_d3(Geom g, Op op, int tiles_y, int tiles_z,
                                                   int tc, double* partials) {
     using Acc = typename Op::acc_t;
@@ -1077,7 +1093,7 @@ __global__ __launch_bounds__(BLOCK) void k_mtm_d3(Geom g, Op op, int tiles_y, in
     if (!op.begin()) return;
     const int b = xcd_remap(blockIdx.x, gridDim.x);
     double part[Op::kNP] = {};
-    tile_mtm_d3<Op, NX, TY, TZ, BLOCK>(g, op, tiles_y, tiles_z, tc, b, lds, part);
+    tile_mtm_d3<Op, NX, TY, TZ, BLOCK, PD>(g, op, tiles_y, tiles_z, tc, b, lds, part);
     if constexpr (Op::kReduce) deposit<BLOCK, Op::kNP>(part, partials, b);
 }
 
