@@ -424,7 +424,7 @@ hub_status solve(const Geom& g, const double* sigma, const double* phi, double* 
     const bool mixed = o.bulk == HUB_F32;
     const size_t V = (size_t)g.V;
     const size_t vb = mixed ? 4 : 8;
-    const SweepPlan P = plan_sweep(g, !mixed);
+    const SweepPlan P = plan_sweep(g, !mixed, true);
     auto al = [](size_t b) { return (b + 255) & ~size_t(255); };
     size_t off = 0;
     const size_t o_sc = off; off += al(2 * sizeof(CGScalars));

@@ -123,6 +123,25 @@ def test_cg_full_size_c3(prec):
 
 
 @pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_cg_d3_nx32(prec):
+    """d=3, 32^3 x 5: the FP64 solver's own 32 x 8 x 8 tile and the mixed
+    solver's 32 x 8 x 4 tile, two slices per block with a one-slice last
+    chunk: oracle true residual and distance to the oracle's solution."""
+    olat, lat, sigma, A, phi = _problem(3, 32, 5)
+    hubtest.log_case(f"cg d3 nx32 {prec}")
+    x_o, res_o, (al, be) = oracle.cg(olat, A, phi, tol=TOL, record=True)
+    assert res_o.converged
+    kappa = dense.lanczos_condition(al, be)
+    opts = hub.cg_opts(hub.F64) if prec == "f64" else hub.cg_opts(hub.F32, hub.F16)
+    x, st = _solve(lat, sigma, phi, opts)
+    assert st["status"] == "HUB_OK"
+    assert _true_resid(olat, A, phi, x) <= 1.1 * TOL
+    assert hubtest.rel_err(x, x_o) <= 4 * kappa * TOL
+    if prec == "f64":
+        assert abs(st["iters"] - res_o.iters) <= 0.03 * res_o.iters + 2
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
 def test_cg_d3_nx64(prec):
     """d=3, 64^3 x 4 on the default 64 x 4 x 4 tile (FP64 links for the
     residual, bulk links per precision): oracle true residual and distance to
