@@ -217,7 +217,10 @@ hub_status launch_q(const Geom& g, const SweepPlan& P, const Op& op,
         if constexpr (op_marches<Op>::value) {
             // The bare product takes the marching tile (8 slices per
             // wavefront, all but the last stage's loads issued up front)
-            // unless a pair tile is forced for tuning.
+            // unless a pair tile is forced for tuning.  The plan's deposit
+            // count is the pair tile's, so only ops without a reduction may
+            // march.
+            static_assert(!Op::kReduce, "a marching sweep leaves no pair-tile deposits");
             if (d1p_tile_override() < 0) {
                 constexpr int kTS = 8, kPF = 8;
                 const int tx = kD1PShapes[P.variant].tx;
