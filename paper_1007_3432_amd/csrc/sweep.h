@@ -216,12 +216,16 @@ hub_status launch_q(const Geom& g, const SweepPlan& P, const Op& op,
     if (P.kind == kSweepD1 && P.pair) {
         if constexpr (op_marches<Op>::value) {
             // The bare product takes the marching tile (8 slices per
-            // wavefront, all but the last stage's loads issued up front)
-            // unless a pair tile is forced for tuning.  The plan's deposit
+            // wavefront, all but the last stage's loads issued up front) on
+            // lattices of 2^19 sites and more, unless a pair tile is forced
+            // for tuning.  Measured on MI355X: at 2^20 sites and above the
+            // marching tile is faster (d=1 2048x512 streamed from HBM 8.0 ->
+            // 6.8 us), at 2^18 and below the shorter chains of the two-slice
+            // tile win (d=1 1024x256: 2.8 vs 4.2 us).  The plan's deposit
             // count is the pair tile's, so only ops without a reduction may
             // march.
             static_assert(!Op::kReduce, "a marching sweep leaves no pair-tile deposits");
-            if (d1p_tile_override() < 0) {
+            if (d1p_tile_override() < 0 && g.V >= (1 << 19)) {
                 constexpr int kTS = 8, kPF = 8;
                 const int tx = kD1PShapes[P.variant].tx;
                 const int ntiles = P.tiles_x * ceil_div(g.nt, kTS);
