@@ -23,6 +23,10 @@ SHAPES = [
     (1, 32, 64), (1, 2, 2), (1, 2, 3), (1, 3, 2), (1, 5, 7), (1, 37, 9), (1, 64, 8),
     (1, 255, 17), (1, 256, 16), (1, 300, 20), (1, 1000, 13), (1, 2048, 512),
     (1, 65, 6), (1, 129, 5), (1, 130, 6), (1, 258, 4), (1, 642, 3),
+    # 2^19 sites and more take the marching d=1 tile (8 slices per wavefront):
+    # a 6-site last strip and a 3-slice last tile; a one-pair last strip
+    # (nx = 2 mod 128); a one-slice last tile
+    (1, 1030, 515), (1, 2050, 260), (1, 4096, 129), (1, 130, 4100), (1, 300, 1800),
     (2, 2, 2), (2, 5, 4), (2, 8, 6),
     (3, 2, 2), (3, 3, 5), (3, 4, 6), (3, 8, 80), (3, 5, 3), (3, 16, 160),
 ]
