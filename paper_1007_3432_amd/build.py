@@ -17,7 +17,8 @@ OUT = os.path.join(HERE, "_build")
 LIB = os.path.join(OUT, "libhub.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
-SOURCES = ["apply.hip", "mtm.hip", "cg.hip", "cheb.hip", "hmc.hip", "serve.hip", "capi.cpp"]
+SOURCES = ["apply.hip", "mtm.hip", "cg.hip", "cgsmall.hip", "cheb.hip", "hmc.hip", "serve.hip",
+           "capi.cpp"]
 
 CFLAGS = [
     "-x", "hip", "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",

@@ -420,8 +420,11 @@ namespace {
 hub_status solve(const Geom& g, const double* sigma, const double* phi, double* x,
                  const hub_cg_opts& o, const hub_cheb_opts* cheb, hub_cg_stats* out,
                  hipStream_t st) {
-    HUB_TRY(g_ctx.ensure());
     const bool mixed = o.bulk == HUB_F32;
+    // A lattice that fits one workgroup is solved inside it: the iteration is
+    // then bound by barriers, not by three kernel launches.
+    if (!mixed && !cheb && cg_small_fits(g)) return cg_solve_small(g, sigma, phi, x, o, out, st);
+    HUB_TRY(g_ctx.ensure());
     const size_t V = (size_t)g.V;
     const size_t vb = mixed ? 4 : 8;
     const SweepPlan P = plan_sweep(g, !mixed, true);

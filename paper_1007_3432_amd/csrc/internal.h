@@ -50,6 +50,11 @@ hub_status cg_solve(const Geom& g, const double* sigma, const double* phi,
                     double* x, const hub_cg_opts& o, hub_cg_stats* out,
                     hipStream_t st);
 
+// FP64 CG in one workgroup for lattices that fit it (cgsmall.hip).
+bool cg_small_fits(const Geom& g);
+hub_status cg_solve_small(const Geom& g, const double* sigma, const double* phi, double* x,
+                          const hub_cg_opts& o, hub_cg_stats* out, hipStream_t st);
+
 // HMC (hmc.hip; arguments already validated).
 hub_status hmc_force(const Geom& g, const double* sigma, const double* x, double* F,
                      hipStream_t st);
