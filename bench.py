@@ -61,7 +61,7 @@ RELIABLE_BYTES = 60
 # on d=1 2048 x 512) actually moves: rocprofv3 FETCH_SIZE x 2.000 plus
 # WRITE_SIZE x 1.000 per dispatch, each factor calibrated on a 256 MiB copy.
 # Valid only for that kernel and tile; None once either changes.
-SWEEP_TRAFFIC = {"kernel": "k_mtm_d1m<OpApply<double>,512,8,8>", "bytes": 25_676_749}
+SWEEP_TRAFFIC = {"kernel": "k_mtm_d1m<OpApply<double>,512,8,8>", "bytes": 25_678_587}
 
 
 def _args():
