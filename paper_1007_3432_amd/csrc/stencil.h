@@ -883,12 +883,17 @@ constexpr int d3_lds_elems() {
 
 // One tile b of the sweep (block of BLOCK lanes); adds this lane's share of
 // the op's sums to part.  lds: d3_lds_elems<NX, TY, TZ>() elements.
-template <class Op, int NX, int TY, int TZ, int BLOCK, int PD = 1>
+// TCU > 0: every block marches exactly TCU slices (the caller guarantees
+// tc == TCU and nt % TCU == 0), and the march is unrolled completely, so
+// that no register holding a load in flight has to be copied where the loop
+// would close.
+template <class Op, int NX, int TY, int TZ, int BLOCK, int PD = 1, int TCU = 0>
 __device__ __forceinline__ void tile_mtm_d3(const Geom& g, const Op& op, int tiles_y,
                                             int tiles_z, int tc, int b,
                                             typename Op::acc_t* lds,
                                             double (&part)[Op::kNP]) {
     static_assert(PD == 1 || PD == 2, "prefetch depth 1 or 2 slices");
+    static_assert(TCU == 0 || TCU >= PD, "an unrolled march covers the prefetch depth");
     using Acc = typename Op::acc_t;
     using Center = typename Op::center_t;
     using Raw = typename Op::raw_t;
@@ -911,7 +916,7 @@ __device__ __forceinline__ void tile_mtm_d3(const Geom& g, const Op& op, int til
     const int iz = b % tiles_z;
     const int ch = b / tiles_z;
     const int y0 = iy * TY, z0 = iz * TZ, s0 = ch * tc;
-    const int h = min(tc, nt - s0);
+    const int h = TCU > 0 ? TCU : min(tc, nt - s0);
     const int t = threadIdx.x;
     const Acc kappa = (Acc)g.kappa;
 
@@ -1051,10 +1056,10 @@ __device__ __forceinline__ void tile_mtm_d3(const Geom& g, const Op& op, int til
 
     // Step r emits z on slice s0 + r; the slice it stages was loaded PD
     // steps earlier into the buffer of parity r (PD = 2) or the one buffer.
-    auto step = [&](int r, Pre& P) {
+    auto step = [&](int r, Pre& P, bool more) {
         const int s = s0 + r;
         stage(P, wrap1(s + 1, nt));
-        if (r + PD < h) prefetch(P, wrap1(s + 1 + PD, nt));
+        if (more) prefetch(P, wrap1(s + 1 + PD, nt));
         __syncthreads();
         Acc yo[NC], yh[NHY];
 #pragma unroll
@@ -1083,17 +1088,20 @@ __device__ __forceinline__ void tile_mtm_d3(const Geom& g, const Op& op, int til
 #pragma unroll
         for (int k = 0; k < NHY; ++k) Y[hyi[k]] = yh[k];
     };
-    if constexpr (PD == 1) {
-        for (int r = 0; r < h; ++r) step(r, pre0);
+    if constexpr (TCU > 0) {
+#pragma unroll
+        for (int r = 0; r < TCU; ++r) step(r, (PD == 2 && (r & 1)) ? pre1 : pre0, r + PD < TCU);
+    } else if constexpr (PD == 1) {
+        for (int r = 0; r < h; ++r) step(r, pre0, r + 1 < h);
     } else {
         for (int r = 0; r < h; r += 2) {
-            step(r, pre0);
-            if (r + 1 < h) step(r + 1, pre1);
+            step(r, pre0, r + 2 < h);
+            if (r + 1 < h) step(r + 1, pre1, r + 3 < h);
         }
     }
 }
 
-template <class Op, int NX, int TY, int TZ, int BLOCK, int PD = 1>
+template <class Op, int NX, int TY, int TZ, int BLOCK, int PD = 1, int TCU = 0>
 __global__ __launch_bounds__(BLOCK) void k_mtm_d3(Geom g, Op op, int tiles_y, int tiles_z,
                                                   int tc, double* partials) {
     using Acc = typename Op::acc_t;
@@ -1102,7 +1110,7 @@ __global__ __launch_bounds__(BLOCK) void k_mtm_d3(Geom g, Op op, int tiles_y, in
     if (!op.begin()) return;
     const int b = xcd_remap(blockIdx.x, gridDim.x);
     double part[Op::kNP] = {};
-    tile_mtm_d3<Op, NX, TY, TZ, BLOCK, PD>(g, op, tiles_y, tiles_z, tc, b, lds, part);
+    tile_mtm_d3<Op, NX, TY, TZ, BLOCK, PD, TCU>(g, op, tiles_y, tiles_z, tc, b, lds, part);
     if constexpr (Op::kReduce) deposit<BLOCK, Op::kNP>(part, partials, b);
 }
 

@@ -205,6 +205,20 @@ constexpr int d3_prefetch_depth() {
     return sizeof(typename Op::acc_t) == 4 ? 2 : 1;
 }
 
+// Slices per block of the completely unrolled d = 3 march, and whether a
+// plan can take it (every block marching exactly that many slices).  Only
+// the bare FP64 product takes it, with two slices in flight: 32^3 x 256
+// 58.0 -> 55.0 us; the FP64 CG phase A would spill registers on it (140 ->
+// 198 us per iteration), the mixed one gains nothing.
+constexpr int kD3Unroll = 16;
+inline bool d3_unrolled_ok(const Geom& g, const SweepPlan& P) {
+    return P.tc == kD3Unroll && g.nt % kD3Unroll == 0;
+}
+template <class Op>
+constexpr int d3_unrolled_depth() {
+    return 2;
+}
+
 // One sweep: z = Q in, consumed by op.out().  y: scratch of g.V acc_t
 // elements, used by the generic path only.  A reducing op's deposits go to
 // partials; with finalize, a one-block kernel then adds them (op.finish),
@@ -292,6 +306,13 @@ hub_status launch_q(const Geom& g, const SweepPlan& P, const Op& op,
         switch (P.variant) {
 #define HUB_D3_CASE(K, NX, TY, TZ, B)                                                    \
     case K:                                                                              \
+        if constexpr (NX >= 32 && op_marches<Op>::value) {                               \
+            if (d3_unrolled_ok(g, P)) {                                                  \
+                k_mtm_d3<Op, NX, TY, TZ, B, d3_unrolled_depth<Op>(), kD3Unroll>            \
+                    <<<P.grid, B, 0, st>>>(g, op, P.tiles_y, P.tiles_z, P.tc, partials);  \
+                break;                                                                   \
+            }                                                                            \
+        }                                                                                \
         k_mtm_d3<Op, NX, TY, TZ, B, d3_prefetch_depth<Op>()>                              \
             <<<P.grid, B, 0, st>>>(g, op, P.tiles_y, P.tiles_z, P.tc, partials);          \
         break;

@@ -141,6 +141,24 @@ def test_apply_full_size_c3_fp64():
     assert hubtest.rel_err(z_d.cpu().numpy(), oracle.apply_MtM(olat, A, x)) <= 1e-13
 
 
+@pytest.mark.parametrize("shape", [(3, 32, 256), (3, 64, 16)], ids=["32x256", "64x16"])
+def test_apply_d3_unrolled_march(shape):
+    """Lattices on which every block of the bare FP64 product marches exactly
+    16 slices take the completely unrolled march with two slices in flight:
+    element-wise against the oracle on every site."""
+    d, nx, nt = shape
+    olat, lat = _lat(d, nx, nt, mu=0.02)
+    hubtest.log_case(f"apply fp64 unrolled march {shape}")
+    sigma, _ = inputs.sigma_eta(d, nx, nt, seed=9)
+    x = inputs.random_vector(olat.volume, 10)
+    A = oracle.links(olat, sigma)
+    z_d = hubtest.empty(lat.volume, hub.F64)
+    hub.hub_apply_MtM(lat, hubtest.to_dev(A), hub.F64, hub.F64, hubtest.to_dev(x), z_d)
+    z, z_ref = z_d.cpu().numpy(), oracle.apply_MtM(olat, A, x)
+    assert hubtest.rel_err(z, z_ref) <= 1e-13
+    assert np.max(np.abs(z - z_ref)) <= 1e-13 * np.max(np.abs(z_ref))
+
+
 @pytest.mark.parametrize("vec", [hub.F64, hub.F32], ids=["f64", "f32"])
 def test_apply_d3_nx64(vec):
     """d=3, 64^3 x 4 (1 048 576 sites): the default 64 x 4 x 4 tile of the
