@@ -123,11 +123,14 @@ HUB_API hub_status hub_apply_MtM(const hub_lattice* lat, const void* links,
  *   accumulated in FP64; every opts->reliable_every iterations (and whenever
  *   the iterated residual meets tol) x += x_lo is folded into the FP64
  *   solution and r is replaced by the FP64 true residual phi - Q x.
- * Convergence is always decided on the FP64 true residual.  The workspace
- * is allocated on each call with hipMallocAsync on `stream` (the runtime's
- * memory pool keeps the memory for the next call) and freed before the call
- * returns; the HIP graphs of the iteration chunks are captured on each call
- * too.  Blocks until done.
+ * Convergence is always decided on the FP64 true residual.  With bulk =
+ * HUB_F64 on a lattice of at most 2048 sites the whole solve runs in one
+ * workgroup (one kernel launch, no graphs); otherwise each iteration is a few
+ * kernels replayed in chunks from HIP graphs.  The workspace is allocated on
+ * each call with hipMallocAsync on `stream` (the runtime's memory pool keeps
+ * the memory for the next call) and freed before the call returns; the HIP
+ * graphs of the iteration chunks are captured on each call too.  Blocks
+ * until done.  stats.reliable_updates counts the true-residual recomputes.
  * Returns HUB_OK, or HUB_E_NOCONV with x holding the last iterate and
  * `out` filled; `out` may be NULL. */
 HUB_API hub_status hub_cg_solve(const hub_lattice* lat, const double* sigma,
