@@ -74,8 +74,9 @@ def test_stencil_equals_premultiplied_block_form(case):
 
 
 def test_trotter_residual_is_second_order():
-    """The stencil form agrees with the block form up to O(dtau^2) (Sec. 2,
-    'up to second order'): |1 + dtau K - exp(dtau K)| shrinks 4x per halving."""
+    """The stencil form agrees with the block form to O(dtau^2) (Sec. 2, the
+    order the paper gives for the stencil): |1 + dtau K - exp(dtau K)| shrinks
+    4x per halving."""
     K = dense.kinetic_matrix(3, 4, 1.0)
     errs = []
     for dtau in (0.02, 0.01, 0.005):
