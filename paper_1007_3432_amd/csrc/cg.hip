@@ -95,8 +95,8 @@ __global__ __launch_bounds__(256) void k_phaseB_fused(const CGScalars* __restric
     } else {
 #pragma unroll
         for (int k = 0; k < 8; ++k) {
-            rv[k] = k < cnt ? r[base + k] : (Vec)0;
-            qv[k] = k < cnt ? q[base + k] : (Vec)0;
+            rv[k] = k < cnt ? r[base + eoff(k)] : (Vec)0;
+            qv[k] = k < cnt ? q[base + eoff(k)] : (Vec)0;
         }
     }
     const double pq = reduce_deposits_canon(dep_pq, n_pq);
@@ -123,7 +123,7 @@ __global__ __launch_bounds__(256) void k_phaseB_fused(const CGScalars* __restric
     } else {
 #pragma unroll
         for (int k = 0; k < 8; ++k)
-            if (k < cnt) r[base + k] = rv[k];
+            if (k < cnt) r[base + eoff(k)] = rv[k];
     }
     deposit<256, 1>(part, dep_rr, blockIdx.x);
 }

@@ -8,32 +8,34 @@
 
 namespace hub {
 
-// Sites per element-wise tile: 256 lanes x 8 consecutive sites, lane t
-// handling sites tile*kETile + 8t .. 8t+7 with 16-byte vector accesses.
+// Sites per element-wise tile: 256 lanes x 8 sites.  Lane t handles the
+// site pairs tile*kETile + 512 j + 2t, +1 (j = 0..3): each access of a
+// wavefront is one contiguous run (1 KiB for FP64, 512 B for FP32).
 constexpr int kETile = 2048;
+
+// Offset of a lane's element k (0..7) from its first site; increasing in k,
+// so the elements inside [0, V) are always a prefix.
+__host__ __device__ constexpr int eoff(int k) { return 512 * (k >> 1) + (k & 1); }
 
 __host__ __device__ inline int elem_tiles(int V) { return (V + kETile - 1) / kETile; }
 
-// Eight consecutive elements starting at p (16-byte aligned when full).
+// A lane's eight elements from its first site p (pairs aligned to 8 bytes
+// per element).
 template <class T>
 __device__ __forceinline__ void ld8(const T* __restrict__ p, T (&v)[8]) {
     if constexpr (sizeof(T) == 8) {
-        const double2* q = reinterpret_cast<const double2*>(p);
 #pragma unroll
-        for (int k = 0; k < 4; ++k) {
-            const double2 w = q[k];
-            v[2 * k] = w.x;
-            v[2 * k + 1] = w.y;
+        for (int j = 0; j < 4; ++j) {
+            const double2 w = *reinterpret_cast<const double2*>(p + eoff(2 * j));
+            v[2 * j] = w.x;
+            v[2 * j + 1] = w.y;
         }
     } else {
-        const float4* q = reinterpret_cast<const float4*>(p);
 #pragma unroll
-        for (int k = 0; k < 2; ++k) {
-            const float4 w = q[k];
-            v[4 * k] = w.x;
-            v[4 * k + 1] = w.y;
-            v[4 * k + 2] = w.z;
-            v[4 * k + 3] = w.w;
+        for (int j = 0; j < 4; ++j) {
+            const float2 w = *reinterpret_cast<const float2*>(p + eoff(2 * j));
+            v[2 * j] = w.x;
+            v[2 * j + 1] = w.y;
         }
     }
 }
@@ -41,22 +43,24 @@ __device__ __forceinline__ void ld8(const T* __restrict__ p, T (&v)[8]) {
 template <class T>
 __device__ __forceinline__ void st8(T* __restrict__ p, const T (&v)[8]) {
     if constexpr (sizeof(T) == 8) {
-        double2* q = reinterpret_cast<double2*>(p);
 #pragma unroll
-        for (int k = 0; k < 4; ++k) q[k] = make_double2(v[2 * k], v[2 * k + 1]);
+        for (int j = 0; j < 4; ++j)
+            *reinterpret_cast<double2*>(p + eoff(2 * j)) = make_double2(v[2 * j], v[2 * j + 1]);
     } else {
-        float4* q = reinterpret_cast<float4*>(p);
 #pragma unroll
-        for (int k = 0; k < 2; ++k)
-            q[k] = make_float4(v[4 * k], v[4 * k + 1], v[4 * k + 2], v[4 * k + 3]);
+        for (int j = 0; j < 4; ++j)
+            *reinterpret_cast<float2*>(p + eoff(2 * j)) = make_float2(v[2 * j], v[2 * j + 1]);
     }
 }
 
 // Lane's first site and how many of its 8 sites are inside [0, V).
-__device__ __forceinline__ int lane_base(int tile) { return tile * kETile + 8 * threadIdx.x; }
+__device__ __forceinline__ int lane_base(int tile) { return tile * kETile + 2 * threadIdx.x; }
+// How many of the lane's elements lie inside [0, V) (a prefix).
 __device__ __forceinline__ int lane_count(int base, int V) {
-    const int c = V - base;
-    return c >= 8 ? 8 : (c < 0 ? 0 : c);
+    int c = 0;
+#pragma unroll
+    for (int k = 0; k < 8; ++k) c += base + eoff(k) < V ? 1 : 0;
+    return c;
 }
 
 // r = phi, p0 = 0, x = 0 (x_lo = 0); part[0] += phi.phi.
@@ -71,7 +75,7 @@ __device__ __forceinline__ void tile_init(const double* __restrict__ phi, RVec* 
         ld8(phi + base, f);
     } else {
 #pragma unroll
-        for (int k = 0; k < 8; ++k) f[k] = k < cnt ? phi[base + k] : 0.0;
+        for (int k = 0; k < 8; ++k) f[k] = k < cnt ? phi[base + eoff(k)] : 0.0;
     }
     RVec rv[8], zr[8];
     double zd[8];
@@ -93,10 +97,10 @@ __device__ __forceinline__ void tile_init(const double* __restrict__ phi, RVec* 
 #pragma unroll
         for (int k = 0; k < 8; ++k)
             if (k < cnt) {
-                r[base + k] = rv[k];
-                p0[base + k] = (RVec)0;
-                x[base + k] = 0.0;
-                if (xlo) xlo[base + k] = 0.0f;
+                r[base + eoff(k)] = rv[k];
+                p0[base + eoff(k)] = (RVec)0;
+                x[base + eoff(k)] = 0.0;
+                if (xlo) xlo[base + eoff(k)] = 0.0f;
             }
     }
 }
@@ -133,8 +137,8 @@ __device__ __forceinline__ void tile_phaseB(Vec* __restrict__ r, const Vec* __re
     } else {
 #pragma unroll
         for (int k = 0; k < 8; ++k) {
-            rv[k] = k < cnt ? r[base + k] : (Vec)0;
-            qv[k] = k < cnt ? q[base + k] : (Vec)0;
+            rv[k] = k < cnt ? r[base + eoff(k)] : (Vec)0;
+            qv[k] = k < cnt ? q[base + eoff(k)] : (Vec)0;
         }
     }
 #pragma unroll
@@ -147,7 +151,7 @@ __device__ __forceinline__ void tile_phaseB(Vec* __restrict__ r, const Vec* __re
     } else {
 #pragma unroll
         for (int k = 0; k < 8; ++k)
-            if (k < cnt) r[base + k] = rv[k];
+            if (k < cnt) r[base + eoff(k)] = rv[k];
     }
 }
 
@@ -199,9 +203,9 @@ __device__ __forceinline__ void tile_fold(double* __restrict__ x, float* __restr
     } else {
 #pragma unroll
         for (int k = 0; k < 8; ++k) {
-            xv[k] = k < cnt ? x[base + k] : 0.0;
-            pv[k] = k < cnt ? p[base + k] : (PVec)0;
-            lv[k] = (xlo && k < cnt) ? xlo[base + k] : 0.0f;
+            xv[k] = k < cnt ? x[base + eoff(k)] : 0.0;
+            pv[k] = k < cnt ? p[base + eoff(k)] : (PVec)0;
+            lv[k] = (xlo && k < cnt) ? xlo[base + eoff(k)] : 0.0f;
         }
     }
     if (!xlo) {
@@ -221,8 +225,8 @@ __device__ __forceinline__ void tile_fold(double* __restrict__ x, float* __restr
 #pragma unroll
         for (int k = 0; k < 8; ++k)
             if (k < cnt) {
-                x[base + k] = xv[k];
-                if (xlo) xlo[base + k] = 0.0f;
+                x[base + eoff(k)] = xv[k];
+                if (xlo) xlo[base + eoff(k)] = 0.0f;
             }
     }
 }

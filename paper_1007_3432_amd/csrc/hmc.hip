@@ -74,9 +74,9 @@ __global__ __launch_bounds__(256) void k_energy(const double* __restrict__ pi,
     } else {
 #pragma unroll
         for (int k = 0; k < 8; ++k) {
-            a[k] = k < cnt ? pi[base + k] : 0.0;
-            f[k] = k < cnt ? phi[base + k] : 0.0;
-            y[k] = k < cnt ? x[base + k] : 0.0;
+            a[k] = k < cnt ? pi[base + eoff(k)] : 0.0;
+            f[k] = k < cnt ? phi[base + eoff(k)] : 0.0;
+            y[k] = k < cnt ? x[base + eoff(k)] : 0.0;
         }
     }
     double part[2] = {0.0, 0.0};
