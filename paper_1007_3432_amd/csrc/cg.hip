@@ -137,18 +137,16 @@ __global__ __launch_bounds__(256) void k_phaseB_finish(CGScalars* sc, const doub
 }
 
 // As k_phaseB_finish, reading the state from sc_in and writing it to sc_out.
+// The sum does not depend on the state, so its loads go out first, beside
+// the load of the state; a finished solve's state is only copied.
 __global__ __launch_bounds__(256) void k_phaseB_finish_to(const CGScalars* __restrict__ sc_in,
                                                           CGScalars* __restrict__ sc_out,
                                                           const double* partials, int n) {
-    if (sc_in->done != kRunning) {
-        if (threadIdx.x == 0) *sc_out = *sc_in;
-        return;
-    }
     double tot[1];
     reduce_deposits<256, 1>(partials, n, tot);
     if (threadIdx.x == 0) {
         CGScalars s = *sc_in;
-        finish_phaseB(&s, tot[0]);
+        if (s.done == kRunning) finish_phaseB(&s, tot[0]);
         *sc_out = s;
     }
 }
