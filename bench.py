@@ -905,6 +905,10 @@ def main():
         _progress("sweep rates: c1 context, d=3 16^3x160 and 32^3x256, d=1 8192x1024")
         detail["launch_floor_us"] = launch_floor_us()
         detail["sweep_c1_d1_2048x512"] = sweep_rate(hub, (1, 2048, 512), 24, 500)
+        # The same sweeps on one buffer set (25 MB, inside the 256 MB Infinity
+        # Cache): the cache-resident rate, labelled as such, beside the HBM one.
+        detail["sweep_c1_d1_2048x512_cache_resident_1set"] = sweep_rate(
+            hub, (1, 2048, 512), 1, 500)
         detail["sweep_c2_d3_16x160"] = sweep_rate(hub, (3, 16, 160), 24, 500)
         detail["sweep_c3_d3_32x256"] = sweep_rate(hub, (3, 32, 256), 3, 60)
         detail["sweep_d1_8192x1024"] = sweep_rate(hub, (1, 8192, 1024), 3, 60)
