@@ -126,11 +126,14 @@ HUB_API hub_status hub_apply_MtM(const hub_lattice* lat, const void* links,
  * Convergence is always decided on the FP64 true residual.  With bulk =
  * HUB_F64 on a lattice of at most 2048 sites the whole solve runs in one
  * workgroup (one kernel launch, no graphs); otherwise each iteration is a few
- * kernels replayed in chunks from HIP graphs.  The workspace is allocated on
- * each call with hipMallocAsync on `stream` (the runtime's memory pool keeps
- * the memory for the next call) and freed before the call returns; the HIP
- * graphs of the iteration chunks are captured on each call too.  Blocks
- * until done.  stats.reliable_updates counts the true-residual recomputes.
+ * kernels replayed in chunks from HIP graphs.  The device workspace (about
+ * five V-vectors of `bulk` plus the links) and the chunk graphs are kept per
+ * host thread after the call: the next solve on that thread reuses the
+ * workspace when it is large enough (else frees it and allocates a larger
+ * one, which synchronizes the device) and replays the graphs when lattice,
+ * options, phi and x are the same (else captures them again).
+ * hub_solver_release frees them.  Blocks until done, and until `stream` has
+ * drained.  stats.reliable_updates counts the true-residual recomputes.
  * Returns HUB_OK, or HUB_E_NOCONV with x holding the last iterate and
  * `out` filled; `out` may be NULL. */
 HUB_API hub_status hub_cg_solve(const hub_lattice* lat, const double* sigma,
@@ -185,7 +188,7 @@ HUB_API hub_status hub_apply_cheb_noalloc(const hub_lattice* lat, const double* 
  * |r| <= tol |phi| and confirmed on the FP64 true residual; a failed
  * confirmation restarts from the true residual.  stats->iters counts CG
  * iterations (each costs 2n + 1 applications of Q).  Blocks until done;
- * returns as hub_cg_solve. */
+ * keeps its workspace and graphs, and returns, as hub_cg_solve. */
 HUB_API hub_status hub_pcg_solve(const hub_lattice* lat, const double* sigma,
                          const double* phi, double* x, const hub_cg_opts* opts,
                          const hub_cheb_opts* cheb, hub_cg_stats* out,
@@ -287,6 +290,12 @@ HUB_API hub_status hub_serve_poll(hub_server* srv, uint64_t ticket, double* x_ho
 
 /* Stops the worker after the in-flight solves finish and frees everything. */
 HUB_API hub_status hub_serve_destroy(hub_server* srv);
+
+/* Frees the solver workspace and chunk graphs that hub_cg_solve,
+ * hub_pcg_solve and the HMC calls keep for the calling host thread (see
+ * hub_cg_solve).  Safe to call at any time between calls; the next solve
+ * allocates again.  Returns HUB_OK. */
+HUB_API hub_status hub_solver_release(void);
 
 /* Message for the last error on the calling thread ("" if none). */
 HUB_API const char* hub_last_error(void);

@@ -263,6 +263,14 @@ hub_status hub_hmc_trajectory(const hub_lattice* lat, double* sigma, const doubl
     HUB_GUARD_END
 }
 
+hub_status hub_solver_release(void) {
+    HUB_GUARD_BEGIN
+    clear_error();
+    solver_release();
+    return HUB_OK;
+    HUB_GUARD_END
+}
+
 const char* hub_last_error(void) { return last_error(); }
 
 }  // extern "C"

@@ -23,8 +23,11 @@
 // preconditioned solver keeps the one-block finalize after phase A as well
 // (its preconditioner's 2n sweeps dwarf it).
 #include <algorithm>
+#include <array>
 #include <cmath>
+#include <cstdint>
 #include <cstdlib>
+#include <cstring>
 
 #include "cgtiles.h"
 #include "cheb.h"
@@ -176,20 +179,74 @@ namespace {
 // that the FP32 recurrence never runs far ahead of the FP64 residual.
 constexpr double kReliableDelta = 0.1;
 
-// Pinned per-thread snapshot buffers and events for the chunk pipeline.
+// Everything a captured chunk graph depends on besides device memory
+// contents: geometry, options, preconditioner, the caller's phi and x, the
+// workspace address.  Two solves with equal keys replay the same graphs.
+using SolveKey = std::array<uint64_t, 20>;
+
+inline uint64_t bits_of(double v) {
+    uint64_t u;
+    std::memcpy(&u, &v, sizeof u);
+    return u;
+}
+
+// Per host thread: pinned snapshot buffers, events and the stream of the
+// chunk pipeline, and the last solve's workspace and chunk graphs, kept for
+// the next solve.  Freeing the workspace after every call would return its
+// pages to the driver, and the page-table update that follows slows the
+// caller's next kernels (measured on MI355X: the d=1 2048x512 sweep after a
+// solve 6.71 us instead of 6.53 us); capturing two graphs per call costs host
+// time the device waits for.
 struct HostCtx {
     int device = -1;
     CGScalars* snap = nullptr;  // [2], pinned
     hipEvent_t ev[2] = {nullptr, nullptr};
     hipEvent_t t0 = nullptr, t1 = nullptr, in_ev = nullptr;
     hipStream_t stream = nullptr;  // the solve runs (and is captured) here
+    char* ws = nullptr;            // solver workspace (hipMalloc), ws_bytes long
+    size_t ws_bytes = 0;
+    hipGraphExec_t gex[2] = {nullptr, nullptr};  // chunk graphs, valid for gkey
+    bool gvalid = false;
+    SolveKey gkey{};
     ~HostCtx() {
         if (device < 0) return;
         (void)hipSetDevice(device);
+        release();
         if (snap) (void)hipHostFree(snap);
         for (auto e : {ev[0], ev[1], t0, t1, in_ev})
             if (e) (void)hipEventDestroy(e);
         if (stream) (void)hipStreamDestroy(stream);
+    }
+    void drop_graphs() {
+        for (auto& e : gex) {
+            if (e) (void)hipGraphExecDestroy(e);
+            e = nullptr;
+        }
+        gvalid = false;
+    }
+    // Frees the cached workspace and graphs (no solve may be running on
+    // this thread: every solve has returned, so none is).
+    void release() {
+        drop_graphs();
+        if (ws) (void)hipFree(ws);
+        ws = nullptr;
+        ws_bytes = 0;
+    }
+    // A workspace of at least `bytes`, reusing the cached one when it is
+    // large enough.  Growing it drops the graphs, which point into it.
+    hub_status workspace(size_t bytes, char** out) {
+        if (bytes > ws_bytes) {
+            release();
+            if (hipMalloc((void**)&ws, bytes) != hipSuccess) {
+                (void)hipGetLastError();
+                ws = nullptr;
+                return set_error(HUB_E_NOMEM,
+                                 "hub_cg_solve: cannot allocate %zu bytes of workspace", bytes);
+            }
+            ws_bytes = bytes;
+        }
+        *out = ws;
+        return HUB_OK;
     }
     hub_status ensure() {
         int dev = 0;
@@ -238,6 +295,7 @@ struct Solver {
     std::vector<ChebFactor> cheb;
     double* z = nullptr;
     double* w = nullptr;
+    SolveKey key{};  // what the chunk graphs depend on
 
     hub_status fold_and_residual(int mode) {
         k_fold<Vec><<<elem_tiles(g.V), 256, 0, st>>>(sc, mode, x, xlo, p0, p1, g.V);
@@ -304,14 +362,6 @@ inline bool use_graphs() {
     return v;
 }
 
-struct GraphPair {
-    hipGraphExec_t ex[2] = {nullptr, nullptr};
-    ~GraphPair() {
-        for (auto e : ex)
-            if (e) (void)hipGraphExecDestroy(e);
-    }
-};
-
 template <class Vec, class Lnk>
 hub_status capture_chunk(Solver<Vec, Lnk>& S, int iters, CGScalars* snap, bool mixed,
                          hipGraphExec_t* out) {
@@ -354,15 +404,20 @@ hub_status run_solver(Solver<Vec, Lnk>& S, bool mixed, hub_cg_stats* out) {
     const int C = mixed ? o.reliable_every
                         : (S.cheb.empty() ? 50
                                           : std::max(2, 200 / (2 * (int)S.cheb.size() + 1)));
-    GraphPair G;
+    // The chunk graphs of the previous solve on this thread are replayed
+    // when nothing they depend on has changed; otherwise they are captured
+    // again.
     const bool graphs = use_graphs();
-    if (graphs) {
-        HUB_TRY(capture_chunk(S, C, &H.snap[0], mixed, &G.ex[0]));
-        HUB_TRY(capture_chunk(S, C, &H.snap[1], mixed, &G.ex[1]));
+    if (graphs && !(H.gvalid && H.gkey == S.key)) {
+        H.drop_graphs();
+        HUB_TRY(capture_chunk(S, C, &H.snap[0], mixed, &H.gex[0]));
+        HUB_TRY(capture_chunk(S, C, &H.snap[1], mixed, &H.gex[1]));
+        H.gkey = S.key;
+        H.gvalid = true;
     }
     auto enqueue = [&](int slot) -> hub_status {
         if (graphs) {
-            HUB_HIP(hipGraphLaunch(G.ex[slot], st));
+            HUB_HIP(hipGraphLaunch(H.gex[slot], st));
         } else {
             HUB_TRY(S.chunk(C, &H.snap[slot], mixed));
         }
@@ -442,10 +497,17 @@ hub_status solve(const Geom& g, const double* sigma, const double* phi, double* 
     const size_t o_z = off; off += cheb ? al(8 * V) : 0;
     const size_t o_w = off; off += cheb ? al(8 * V) : 0;
     char* ws = nullptr;
-    if (hipMallocAsync((void**)&ws, off, st) != hipSuccess) {
-        (void)hipGetLastError();
-        return set_error(HUB_E_NOMEM, "hub_cg_solve: cannot allocate %zu bytes of workspace", off);
-    }
+    HUB_TRY(g_ctx.workspace(off, &ws));
+    const double cheb_scale =
+        cheb ? (cheb->scale > 0 ? cheb->scale : cheb_default_scale(g)) : 0.0;
+    const SolveKey key = {(uint64_t)g.d, (uint64_t)g.nx, (uint64_t)g.nt, bits_of(g.kappa),
+                          bits_of(g.lscale), bits_of(g.b), (uint64_t)o.bulk,
+                          (uint64_t)o.link, bits_of(o.tol), (uint64_t)(uint32_t)o.max_iter,
+                          (uint64_t)(uint32_t)o.reliable_every,
+                          cheb ? (uint64_t)(uint32_t)cheb->n : 0,
+                          cheb ? bits_of(cheb->eps) : 0, bits_of(cheb_scale),
+                          (uint64_t)(uintptr_t)phi, (uint64_t)(uintptr_t)x,
+                          (uint64_t)(uintptr_t)ws, (uint64_t)off, 0, 0};
     hub_status result = HUB_OK;
     const double* A64 = (const double*)(ws + o_A64);
     result = launch_links(g, sigma, ws + o_A64, HUB_F64, st);
@@ -466,9 +528,9 @@ hub_status solve(const Geom& g, const double* sigma, const double* phi, double* 
             S.q = (double*)(ws + o_q);
             S.xlo = nullptr;
             S.yscratch = P.fused ? nullptr : (double*)(ws + o_y);
+            S.key = key;
             if (cheb) {
-                const double scale = cheb->scale > 0 ? cheb->scale : cheb_default_scale(g);
-                S.cheb = cheb_factors(cheb->n, cheb->eps, scale);
+                S.cheb = cheb_factors(cheb->n, cheb->eps, cheb_scale);
                 S.z = (double*)(ws + o_z);
                 S.w = (double*)(ws + o_w);
             }
@@ -488,6 +550,7 @@ hub_status solve(const Geom& g, const double* sigma, const double* phi, double* 
             S.q = (float*)(ws + o_q);
             S.xlo = (float*)(ws + o_xlo);
             S.yscratch = P.fused ? nullptr : (double*)(ws + o_y);
+            S.key = key;
             result = run_solver(S, true, out);
         } else {
             Solver<float, Link16> S{g, o, st, P};
@@ -504,14 +567,15 @@ hub_status solve(const Geom& g, const double* sigma, const double* phi, double* 
             S.q = (float*)(ws + o_q);
             S.xlo = (float*)(ws + o_xlo);
             S.yscratch = P.fused ? nullptr : (double*)(ws + o_y);
+            S.key = key;
             result = run_solver(S, true, out);
         }
     }
     // The solve ran on the context stream: let it drain (also on an error
-    // path) before the workspace goes back to the caller's stream.
-    (void)hipStreamSynchronize(g_ctx.stream);
-    hipError_t e = hipFreeAsync(ws, st);
-    hipError_t e2 = hipStreamSynchronize(st);
+    // path) before the workspace can be used again, and let the caller's
+    // stream drain too (the links were computed there).
+    const hipError_t e = hipStreamSynchronize(g_ctx.stream);
+    const hipError_t e2 = hipStreamSynchronize(st);
     if (result == HUB_OK && (e != hipSuccess || e2 != hipSuccess))
         return set_error(HUB_E_DEVICE, "hub_cg_solve: %s",
                          hipGetErrorString(e != hipSuccess ? e : e2));
@@ -519,6 +583,15 @@ hub_status solve(const Geom& g, const double* sigma, const double* phi, double* 
 }
 
 }  // namespace
+
+hub_status solver_workspace(size_t bytes, char** out) {
+    HUB_TRY(g_ctx.ensure());
+    return g_ctx.workspace(bytes, out);
+}
+
+// Nothing of this thread's runs on the context stream: every solve waits
+// for its work before returning.
+void solver_release() { g_ctx.release(); }
 
 hub_status cg_solve(const Geom& g, const double* sigma, const double* phi, double* x,
                     const hub_cg_opts& o, hub_cg_stats* out, hipStream_t st) {

@@ -226,11 +226,8 @@ hub_status cg_solve_small(const Geom& g, const double* sigma, const double* phi,
                           const hub_cg_opts& o, hub_cg_stats* out, hipStream_t st) {
     const size_t bytes = (8 * (size_t)g.V + 255) / 256 * 256 + 256;
     char* ws = nullptr;
-    if (hipMallocAsync((void**)&ws, bytes, st) != hipSuccess) {
-        (void)hipGetLastError();
-        return set_error(HUB_E_NOMEM, "hub_cg_solve: cannot allocate %zu bytes of workspace",
-                         bytes);
-    }
+    const hub_status wr = solver_workspace(bytes, &ws);
+    if (wr != HUB_OK) return wr;
     double* A = (double*)ws;
     SmallResult* dres = (SmallResult*)(ws + bytes - 256);
     hipEvent_t t0 = nullptr, t1 = nullptr;
@@ -254,8 +251,7 @@ hub_status cg_solve_small(const Geom& g, const double* sigma, const double* phi,
     }
     if (t0) (void)hipEventDestroy(t0);
     if (t1) (void)hipEventDestroy(t1);
-    step(hipFreeAsync(ws, st));
-    step(hipStreamSynchronize(st));
+    step(hipStreamSynchronize(st));  // the workspace is free again once st has drained
     if (r != HUB_OK) return r;
     hub_cg_stats stats{};
     stats.iters = h.iters;

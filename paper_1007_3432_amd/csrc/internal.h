@@ -50,6 +50,14 @@ hub_status cg_solve(const Geom& g, const double* sigma, const double* phi,
                     double* x, const hub_cg_opts& o, hub_cg_stats* out,
                     hipStream_t st);
 
+// The calling thread's solver workspace, at least `bytes` long (cg.hip): kept
+// between solves, grown when a solve needs more; valid until the next call
+// that grows it or solver_release().  Solves only: one solve at a time per
+// thread uses it.
+hub_status solver_workspace(size_t bytes, char** out);
+// Frees the calling thread's solver workspace and cached chunk graphs.
+void solver_release();
+
 // FP64 CG in one workgroup for lattices that fit it (cgsmall.hip).
 bool cg_small_fits(const Geom& g);
 hub_status cg_solve_small(const Geom& g, const double* sigma, const double* phi, double* x,

@@ -142,11 +142,12 @@ def load():
                                      ctypes.POINTER(ctypes.c_uint64)]
     lib.hub_serve_poll.argtypes = [vp, ctypes.c_uint64, vp, ctypes.POINTER(CGStats)]
     lib.hub_serve_destroy.argtypes = [vp]
+    lib.hub_solver_release.argtypes = []
     for f in (lib.hub_links_from_sigma, lib.hub_apply_M, lib.hub_apply_MtM, lib.hub_cg_solve,
               lib.hub_apply_cheb, lib.hub_apply_cheb_noalloc, lib.hub_pcg_solve,
               lib.hub_hmc_force, lib.hub_md_trajectory, lib.hub_hmc_trajectory,
               lib.hub_serve_create, lib.hub_serve_submit, lib.hub_serve_poll,
-              lib.hub_serve_destroy):
+              lib.hub_serve_destroy, lib.hub_solver_release):
         f.restype = ctypes.c_int
     lib.hub_last_error.argtypes = []
     lib.hub_last_error.restype = ctypes.c_char_p
@@ -222,6 +223,10 @@ def hub_cg_solve(lat: Lattice, sigma, phi, x, opts: CGOpts, stream=None,
     ok = (HUB_OK,) if raise_on_noconv else (HUB_OK, HUB_E_NOCONV)
     _check(status, "hub_cg_solve", ok)
     return st.as_dict()
+
+
+def hub_solver_release() -> None:
+    _check(load().hub_solver_release(), "hub_solver_release")
 
 
 def hub_apply_cheb(lat: Lattice, links, r, z, cheb: ChebOpts, stream=None) -> None:

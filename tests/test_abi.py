@@ -20,7 +20,7 @@ def test_header_declares_the_api():
     assert {"hub_links_from_sigma", "hub_apply_M", "hub_apply_MtM", "hub_cg_solve",
             "hub_apply_cheb", "hub_apply_cheb_noalloc", "hub_pcg_solve",
             "hub_hmc_force", "hub_md_trajectory", "hub_hmc_trajectory", "hub_serve_create", "hub_serve_submit", "hub_serve_poll",
-            "hub_serve_destroy", "hub_last_error"} <= names
+            "hub_serve_destroy", "hub_solver_release", "hub_last_error"} <= names
 
 
 def test_every_declared_symbol_is_exported(lib):
@@ -162,3 +162,10 @@ def test_last_error_empty_after_success_path_is_thread_local(lib):
     th.join()
     assert seen == [""]
     assert hub.last_error() != ""
+
+
+def test_solver_release_before_any_solve_is_a_no_op(lib):
+    """Nothing cached yet on this thread: the release touches no device."""
+    assert lib.hub_solver_release() == hub.HUB_OK
+    assert lib.hub_solver_release() == hub.HUB_OK
+    assert hub.last_error() == ""

@@ -158,6 +158,54 @@ def test_cg_d3_nx64(prec):
     assert hubtest.rel_err(x, x_o) <= 4 * kappa * TOL
 
 
+# --- the workspace and chunk graphs a thread keeps between solves
+
+def test_solves_reuse_workspace_and_graphs_bitwise():
+    """Solves on one host thread reuse its workspace and, when lattice,
+    options, phi and x are unchanged, its captured chunk graphs.  A sequence
+    that grows and shrinks the workspace, switches precision, lattice,
+    solver and output buffer, and releases the cache midway, must give
+    bitwise the same x and statistics for the same problem each time, and
+    every x must pass the oracle's true residual."""
+    shapes = {"a": (1, 256, 128), "b": (3, 8, 80), "s": (1, 32, 64)}
+    probs = {k: _problem(*shape) for k, shape in shapes.items()}
+    dev = {k: (hubtest.to_dev(p[2]), hubtest.to_dev(p[4])) for k, p in probs.items()}
+    outs = {k: [hubtest.empty(p[1].volume, hub.F64) for _ in range(2)]
+            for k, p in probs.items()}
+    solvers = {
+        "f64": lambda lat, s, f, x: hub.hub_cg_solve(lat, s, f, x, hub.cg_opts(hub.F64)),
+        "f32": lambda lat, s, f, x: hub.hub_cg_solve(lat, s, f, x, hub.cg_opts(hub.F32, hub.F32)),
+        "f16": lambda lat, s, f, x: hub.hub_cg_solve(lat, s, f, x, hub.cg_opts(hub.F32, hub.F16)),
+        "pcg": lambda lat, s, f, x: hub.hub_pcg_solve(lat, s, f, x, hub.cg_opts(hub.F64),
+                                                      hub.cheb_opts(8, 1e-3)),
+    }
+    seq = [("a", "f64", 0), ("a", "f64", 0), ("a", "f64", 1), ("b", "f32", 0),
+           ("a", "f64", 0), ("s", "f64", 0), ("b", "f16", 1), ("a", "pcg", 0), "release",
+           ("b", "f32", 0), ("a", "f64", 1), ("a", "pcg", 0), ("b", "f32", 0),
+           ("s", "f64", 1), ("b", "f16", 1)]
+    first = {}
+    for n, item in enumerate(seq):
+        if item == "release":
+            hub.hub_solver_release()
+            continue
+        k, how, slot = item
+        hubtest.log_case(f"cached solve {n}: {shapes[k]} {how} out{slot}")
+        olat, _lat, _sigma, A, phi = probs[k]
+        sig_d, phi_d = dev[k]
+        x_d = outs[k][slot]
+        x_d.fill_(float("nan"))  # the output's old contents must not matter
+        st = solvers[how](probs[k][1], sig_d, phi_d, x_d)
+        x = x_d.cpu().numpy()
+        assert _true_resid(olat, A, phi, x) <= TOL * 1.1
+        if (k, how) in first:
+            x0, st0 = first[(k, how)]
+            assert np.array_equal(x, x0), (n, item)
+            assert st["iters"] == st0["iters"], (n, item)
+            assert st["true_rel_resid"] == st0["true_rel_resid"], (n, item)
+        else:
+            first[(k, how)] = (x, st)
+
+
 # --- failure handling (all forced from the host; every kernel exits normally)
 
 def test_max_iter_reports_noconv_with_stats():
