@@ -61,6 +61,8 @@ hub_status make_geom(const hub_lattice* lat, Geom* g) {
     g->kappa = lat->dtau * lat->t_hop;
     g->lscale = std::exp(lat->dtau * lat->mu);
     g->b = std::sqrt(2.0 * (std::exp(-lat->dtau * lat->U) - 1.0));
+    g->fnx = make_fastdiv((uint32_t)g->nx);
+    g->fvs = make_fastdiv((uint32_t)g->vs);
     if (!std::isfinite(g->b) || !std::isfinite(g->lscale))
         return set_error(HUB_E_INVALID, "coupling or chemical potential overflows");
     return HUB_OK;
@@ -88,7 +90,7 @@ __global__ __launch_bounds__(256) void k_links(Geom g, const double* __restrict_
                                                T* __restrict__ out) {
     const int i = blockIdx.x * 256 + threadIdx.x;
     if (i >= g.V) return;
-    const int n = i % g.vs, s = i / g.vs;
+    const int s = fdiv(i, g.fvs), n = i - s * g.vs;
     const int sm = s == 0 ? g.nt - 1 : s - 1;
     const double sn = sin(sigma[n + sm * g.vs]);
     if constexpr (sizeof(T) == 2) {

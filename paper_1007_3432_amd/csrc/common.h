@@ -9,6 +9,28 @@
 
 namespace hub {
 
+// n / d for 0 <= n < 2^31 and 1 <= d < 2^31 by one multiply and a shift
+// (rounded-up multiplier, after Granlund and Montgomery 1994): with
+// s = ceil(log2 d) and m = ceil(2^(32+s) / d), m d = 2^(32+s) + e with
+// 0 <= e < d, so n m / 2^(32+s) exceeds n / d by less than n / 2^(32+s) <
+// 1 / (2d), which never reaches the next integer.  The one-lane-per-site
+// kernels need two to four divisions per site for its coordinates; as
+// integer divisions those cost more than the kernels' memory traffic.
+struct FastDiv {
+    uint64_t m;  // <= 2^33
+    int sh;      // 32 + s
+};
+
+inline FastDiv make_fastdiv(uint32_t d) {
+    int s = 0;
+    while ((1ull << s) < d) ++s;
+    return {((1ull << (32 + s)) + d - 1) / d, 32 + s};
+}
+
+__device__ __forceinline__ int fdiv(int n, const FastDiv& f) {
+    return (int)(((uint64_t)(uint32_t)n * f.m) >> f.sh);
+}
+
 // Lattice geometry and operator constants, passed to kernels by value.
 struct Geom {
     int d;          // spatial dimensions
@@ -19,6 +41,8 @@ struct Geom {
     double kappa;   // dtau * t_hop
     double lscale;  // exp(dtau * mu)
     double b;       // Hubbard-Stratonovich coupling sqrt(2 (exp(-dtau U) - 1))
+    FastDiv fnx;    // division by nx
+    FastDiv fvs;    // division by vs
 };
 
 // Device-resident solver state of one CG solve.  Every field is written by

@@ -23,39 +23,16 @@ enum ForceMode : int {
     kKickDrift = 2,   // pi[i] -= c F, then sigma[i] += eps pi[i]
 };
 
-// n / d for 0 <= n < 2^31 and 1 <= d < 2^31 by one multiply and a shift
-// (rounded-up multiplier, after Granlund and Montgomery 1994): with
-// s = ceil(log2 d) and m = ceil(2^(32+s) / d), m d = 2^(32+s) + e with
-// 0 <= e < d, so n m / 2^(32+s) exceeds n / d by less than n / 2^(32+s) <
-// 1 / (2d), which never crosses the next integer.  The site coordinates of
-// the force kernel need two to four such divisions per site; as integer
-// divisions they cost more than the kernel's memory traffic.
-struct FastDiv {
-    uint64_t m;
-    int sh;
-};
-
-inline FastDiv make_fastdiv(uint32_t d) {
-    int s = 0;
-    while ((1ull << s) < d) ++s;
-    return {((1ull << (32 + s)) + d - 1) / d, 32 + s};
-}
-
-__device__ __forceinline__ int fdiv(int n, const FastDiv& f) {
-    return (int)(((uint64_t)(uint32_t)n * f.m) >> f.sh);
-}
-
 // One lane per site; x at the time-neighbour row and its spatial
 // neighbours come through L1/L2.  Only sigma[i] and pi[i] of the lane's own
 // site are read and written, so the in-place drift is race-free.
 template <int MODE, int D>
-__global__ __launch_bounds__(256) void k_force(Geom g, FastDiv fvs, FastDiv fnx,
-                                               double* __restrict__ sigma,
+__global__ __launch_bounds__(256) void k_force(Geom g, double* __restrict__ sigma,
                                                const double* __restrict__ x,
                                                double* __restrict__ out, double c, double eps) {
     const int i = blockIdx.x * 256 + threadIdx.x;
     if (i >= g.V) return;
-    const int s = fdiv(i, fvs), n = i - s * g.vs;
+    const int s = fdiv(i, g.fvs), n = i - s * g.vs;
     const int sp = s + 1 == g.nt ? 0 : s + 1;
     const int ip = n + sp * g.vs;
     double hop = 0.0;
@@ -63,7 +40,7 @@ __global__ __launch_bounds__(256) void k_force(Geom g, FastDiv fvs, FastDiv fnx,
 #pragma unroll
     for (int j = 0; j < D; ++j) {
         // coordinate j of n; the last one is what is left (< nx)
-        const int q = j + 1 < D ? fdiv(rest, fnx) : 0;
+        const int q = j + 1 < D ? fdiv(rest, g.fnx) : 0;
         const int cj = j + 1 < D ? rest - q * g.nx : rest;
         const int cpj = cj + 1 == g.nx ? 0 : cj + 1;
         const int cmj = cj == 0 ? g.nx - 1 : cj - 1;
@@ -128,8 +105,7 @@ __global__ __launch_bounds__(256) void k_energy_finish(const double* partials, i
 hub_status launch_force(const Geom& g, int mode, double* sigma, const double* x, double* out,
                         double c, double eps, hipStream_t st) {
     const int grid = ceil_div(g.V, 256);
-    const FastDiv fvs = make_fastdiv((uint32_t)g.vs), fnx = make_fastdiv((uint32_t)g.nx);
-#define HUB_FORCE(M, D) k_force<M, D><<<grid, 256, 0, st>>>(g, fvs, fnx, sigma, x, out, c, eps)
+#define HUB_FORCE(M, D) k_force<M, D><<<grid, 256, 0, st>>>(g, sigma, x, out, c, eps)
 #define HUB_FORCE_D(M)                              \
     switch (g.d) {                                  \
         case 1: HUB_FORCE(M, 1); break;             \

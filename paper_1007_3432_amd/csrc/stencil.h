@@ -1121,11 +1121,13 @@ __global__ __launch_bounds__(BLOCK) void k_mtm_d3(Geom g, Op op, int tiles_y, in
 template <class Op>
 __device__ inline typename Op::acc_t gen_M_at(const Geom& g, const Op& op, int i) {
     using Acc = typename Op::acc_t;
-    const int n = i % g.vs, s = i / g.vs;
+    const int s = fdiv(i, g.fvs), n = i - s * g.vs;
     Acc hop = 0;
-    int stride = 1;
+    int stride = 1, rest = n;
     for (int j = 0; j < g.d; ++j) {
-        const int c = (n / stride) % g.nx;
+        const int q = fdiv(rest, g.fnx);
+        const int c = rest - q * g.nx;
+        rest = q;
         const int cp = c + 1 == g.nx ? 0 : c + 1;
         const int cm = c == 0 ? g.nx - 1 : c - 1;
         hop += op_in(op, i + (cp - c) * stride) + op_in(op, i + (cm - c) * stride);
@@ -1153,11 +1155,13 @@ __global__ __launch_bounds__(256) void k_gen_pass2(Geom g, Op op,
     const int i = blockIdx.x * 256 + threadIdx.x;
     double part[Op::kNP] = {};
     if (i < g.V) {
-        const int n = i % g.vs, s = i / g.vs;
+        const int s = fdiv(i, g.fvs), n = i - s * g.vs;
         Acc hop = 0;
-        int stride = 1;
+        int stride = 1, rest = n;
         for (int j = 0; j < g.d; ++j) {
-            const int c = (n / stride) % g.nx;
+            const int q = fdiv(rest, g.fnx);
+            const int c = rest - q * g.nx;
+            rest = q;
             const int cp = c + 1 == g.nx ? 0 : c + 1;
             const int cm = c == 0 ? g.nx - 1 : c - 1;
             hop += y[i + (cp - c) * stride] + y[i + (cm - c) * stride];
@@ -1179,11 +1183,13 @@ template <class Acc, class Vec, class Lnk, bool TRANSPOSE>
 __global__ __launch_bounds__(256) void k_apply_M(Geom g, Lnk lk, const Vec* x, Vec* y) {
     const int i = blockIdx.x * 256 + threadIdx.x;
     if (i >= g.V) return;
-    const int n = i % g.vs, s = i / g.vs;
+    const int s = fdiv(i, g.fvs), n = i - s * g.vs;
     Acc hop = 0;
-    int stride = 1;
+    int stride = 1, rest = n;
     for (int j = 0; j < g.d; ++j) {
-        const int c = (n / stride) % g.nx;
+        const int q = fdiv(rest, g.fnx);
+        const int c = rest - q * g.nx;
+        rest = q;
         const int cp = c + 1 == g.nx ? 0 : c + 1;
         const int cm = c == 0 ? g.nx - 1 : c - 1;
         hop += (Acc)x[i + (cp - c) * stride] + (Acc)x[i + (cm - c) * stride];
