@@ -28,19 +28,27 @@ struct SmallResult {
     double phi2;
 };
 
-// Sum over the block in a fixed order (wave sums, then the waves' sums in
-// wave order), the same value in every lane.  red: kSB / 64 doubles of LDS.
-__device__ inline double sum_block(double v, double* red) {
-    v = wave_sum(v);
-    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-    __syncthreads();  // red[] may still be read by the previous sum
-    if (lane == 0) red[w] = v;
-    __syncthreads();
-    double s = 0.0;
+// Sums over the block in a fixed order (wave sums, then the waves' sums in
+// wave order), the same value in every lane.  Consecutive sums alternate
+// between two LDS slots, so one barrier per sum suffices: a slot is written
+// again only after every lane has passed the other slot's barrier, that is
+// after it has read this slot.  Every lane makes the same sequence of calls.
+struct BlockSum {
+    double* red;  // 2 * kSB / 64 doubles of LDS
+    int turn;
+    __device__ double operator()(double v) {
+        double* r = red + turn * (kSB / 64);
+        turn ^= 1;
+        v = wave_sum(v);
+        const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+        if (lane == 0) r[w] = v;
+        __syncthreads();
+        double s = 0.0;
 #pragma unroll
-    for (int k = 0; k < kSB / 64; ++k) s += red[k];
-    return s;
-}
+        for (int k = 0; k < kSB / 64; ++k) s += r[k];
+        return s;
+    }
+};
 
 struct Site {
     int i;        // linear index (0 for a lane past the end)
@@ -98,7 +106,8 @@ __global__ __launch_bounds__(kSB) void k_cg_small(Geom g, const double* __restri
                                                   double* __restrict__ x_out, double tol2,
                                                   int max_iter, SmallResult* res) {
     __shared__ double P[kSmallSitesMax], Y[kSmallSitesMax], AL[kSmallSitesMax];
-    __shared__ double red[kSB / 64];
+    __shared__ double red[2 * (kSB / 64)];
+    BlockSum sum_block{red, 0};
     Site S[kNPT];
     double x[kNPT], r[kNPT], p[kNPT], f[kNPT];
 #pragma unroll
@@ -129,13 +138,13 @@ __global__ __launch_bounds__(kSB) void k_cg_small(Geom g, const double* __restri
                 part += d * d;
             }
         }
-        return sum_block(part, red);
+        return sum_block(part);
     };
 
     double part = 0.0;
 #pragma unroll
     for (int k = 0; k < kNPT; ++k) part += f[k] * f[k];
-    const double phi2 = sum_block(part, red);
+    const double phi2 = sum_block(part);
     double rho = phi2, rho_true = phi2;
     int done = !isfinite(phi2) ? kDoneBreakdown : (phi2 == 0.0 ? kDoneConverged : kRunning);
     int it = 0, recomputes = 0;
@@ -156,7 +165,7 @@ __global__ __launch_bounds__(kSB) void k_cg_small(Geom g, const double* __restri
             q[k] = S[k].ok ? apply_Mt_at(g, S[k], Y, AL) : 0.0;
             part += p[k] * q[k];
         }
-        const double pq = sum_block(part, red);
+        const double pq = sum_block(part);
         if (!(pq > 0.0) || !isfinite(pq)) {
             done = kDoneBreakdown;
             break;
@@ -176,7 +185,7 @@ __global__ __launch_bounds__(kSB) void k_cg_small(Geom g, const double* __restri
             rn[k] = r[k] - alpha * q[k];
             part += rn[k] * rn[k];
         }
-        double rho_new = sum_block(part, red);
+        double rho_new = sum_block(part);
         if (!isfinite(rho_new)) {
             done = kDoneBreakdown;
             break;
