@@ -27,7 +27,7 @@ inline FastDiv make_fastdiv(uint32_t d) {
     return {((1ull << (32 + s)) + d - 1) / d, 32 + s};
 }
 
-__device__ __forceinline__ int fdiv(int n, const FastDiv& f) {
+__host__ __device__ __forceinline__ int fdiv(int n, const FastDiv& f) {
     return (int)(((uint64_t)(uint32_t)n * f.m) >> f.sh);
 }
 
