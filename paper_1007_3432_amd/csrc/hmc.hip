@@ -64,6 +64,64 @@ __global__ __launch_bounds__(256) void k_force(Geom g, double* __restrict__ sigm
     }
 }
 
+// The same force for even nx, two x-adjacent sites per lane (16-byte loads
+// and stores; the x neighbours of the pair are its own two values and one
+// more site on each side).  Each site's arithmetic is that of k_force, in
+// the same order.
+template <int MODE, int D>
+__global__ __launch_bounds__(256) void k_force2(Geom g, double* __restrict__ sigma,
+                                                const double* __restrict__ x,
+                                                double* __restrict__ out, double c, double eps) {
+    const int i = 2 * (blockIdx.x * 256 + threadIdx.x);  // first site of the pair
+    if (i >= g.V) return;
+    const int s = fdiv(i, g.fvs), n = i - s * g.vs;
+    const int sp = s + 1 == g.nt ? 0 : s + 1;
+    const int ip = n + sp * g.vs;
+    auto ld2v = [](const double* p) { return *reinterpret_cast<const double2*>(p); };
+    const double2 xp = ld2v(x + ip);  // x at the next slice: sites a, b
+    double hop_a = 0.0, hop_b = 0.0;
+    int rest = n, stride = 1;
+#pragma unroll
+    for (int j = 0; j < D; ++j) {
+        const int q = j + 1 < D ? fdiv(rest, g.fnx) : 0;
+        const int cj = j + 1 < D ? rest - q * g.nx : rest;
+        if (j == 0) {
+            // cj is even: a = cj, b = cj + 1 < nx
+            const double left_a = x[ip + (cj == 0 ? g.nx - 1 : -1)];
+            const double right_b = x[ip + (cj + 2 == g.nx ? 2 - g.nx : 2)];
+            hop_a += xp.y + left_a;
+            hop_b += right_b + xp.x;
+        } else {
+            const int cpj = cj + 1 == g.nx ? 0 : cj + 1;
+            const int cmj = cj == 0 ? g.nx - 1 : cj - 1;
+            const double2 pl = ld2v(x + ip + (cpj - cj) * stride);
+            const double2 mi = ld2v(x + ip + (cmj - cj) * stride);
+            hop_a += pl.x + mi.x;
+            hop_b += pl.y + mi.y;
+        }
+        stride *= g.nx;
+        rest = q;
+    }
+    const double sg = sp == 0 ? g.lscale : -g.lscale;
+    const double2 sv = ld2v(sigma + i), xi = ld2v(x + i);
+    double sn_a, cs_a, sn_b, cs_b;
+    sincos(sv.x, &sn_a, &cs_a);
+    sincos(sv.y, &sn_b, &cs_b);
+    const double y_a = xp.x - g.kappa * hop_a + sg * (1.0 + g.b * sn_a) * xi.x;
+    const double y_b = xp.y - g.kappa * hop_b + sg * (1.0 + g.b * sn_b) * xi.y;
+    const double F_a = -2.0 * y_a * (sg * g.b * cs_a) * xi.x;
+    const double F_b = -2.0 * y_b * (sg * g.b * cs_b) * xi.y;
+    if constexpr (MODE == kForceOut) {
+        *reinterpret_cast<double2*>(out + i) = make_double2(F_a, F_b);
+    } else {
+        const double2 po = ld2v(out + i);
+        const double p_a = po.x - c * F_a, p_b = po.y - c * F_b;
+        *reinterpret_cast<double2*>(out + i) = make_double2(p_a, p_b);
+        if constexpr (MODE == kKickDrift)
+            *reinterpret_cast<double2*>(sigma + i) = make_double2(sv.x + eps * p_a, sv.y + eps * p_b);
+    }
+}
+
 // Deposits of 1/2 pi.pi and phi.x (FP64, tile order), then the one-block sum.
 __global__ __launch_bounds__(256) void k_energy(const double* __restrict__ pi,
                                                 const double* __restrict__ phi,
@@ -104,8 +162,16 @@ __global__ __launch_bounds__(256) void k_energy_finish(const double* partials, i
 
 hub_status launch_force(const Geom& g, int mode, double* sigma, const double* x, double* out,
                         double c, double eps, hipStream_t st) {
-    const int grid = ceil_div(g.V, 256);
-#define HUB_FORCE(M, D) k_force<M, D><<<grid, 256, 0, st>>>(g, sigma, x, out, c, eps)
+    // Even nx: two sites per lane (every row, hence V, is even).
+    const bool pairs = (g.nx & 1) == 0;
+    const int grid = pairs ? ceil_div(g.V / 2, 256) : ceil_div(g.V, 256);
+#define HUB_FORCE(M, D)                                                          \
+    do {                                                                         \
+        if (pairs)                                                               \
+            k_force2<M, D><<<grid, 256, 0, st>>>(g, sigma, x, out, c, eps);      \
+        else                                                                     \
+            k_force<M, D><<<grid, 256, 0, st>>>(g, sigma, x, out, c, eps);       \
+    } while (0)
 #define HUB_FORCE_D(M)                              \
     switch (g.d) {                                  \
         case 1: HUB_FORCE(M, 1); break;             \
