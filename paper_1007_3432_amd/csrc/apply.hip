@@ -134,6 +134,18 @@ static hub_status apply_M_t(const Geom& g, Lnk lk, const void* x, void* y,
     return HUB_OK;
 }
 
+// FP64 with even nx: two sites per lane (every row, hence V, is even).
+template <bool TRANSPOSE>
+static void apply_M2_d(const Geom& g, const double* A, const double* x, double* y,
+                       hipStream_t st) {
+    const int grid = ceil_div(g.V / 2, 256);
+    switch (g.d) {
+        case 1: k_apply_M2<TRANSPOSE, 1><<<grid, 256, 0, st>>>(g, A, x, y); break;
+        case 2: k_apply_M2<TRANSPOSE, 2><<<grid, 256, 0, st>>>(g, A, x, y); break;
+        default: k_apply_M2<TRANSPOSE, 3><<<grid, 256, 0, st>>>(g, A, x, y); break;
+    }
+}
+
 Link16 make_link16(const Geom& g, const void* links) {
     Link16 l;
     l.sn = (const _Float16*)links;
@@ -145,6 +157,14 @@ Link16 make_link16(const Geom& g, const void* links) {
 hub_status launch_apply_M(const Geom& g, const void* links, hub_dtype link,
                           hub_dtype vec, const void* x, void* y, int transpose,
                           hipStream_t st) {
+    if (vec == HUB_F64 && (g.nx & 1) == 0) {
+        if (transpose)
+            apply_M2_d<true>(g, (const double*)links, (const double*)x, (double*)y, st);
+        else
+            apply_M2_d<false>(g, (const double*)links, (const double*)x, (double*)y, st);
+        HUB_HIP(hipGetLastError());
+        return HUB_OK;
+    }
     if (vec == HUB_F64)
         return apply_M_t<double, double>(g, Link64{(const double*)links}, x, y, transpose, st);
     if (link == HUB_F32)

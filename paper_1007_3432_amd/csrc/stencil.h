@@ -1207,4 +1207,54 @@ __global__ __launch_bounds__(256) void k_apply_M(Geom g, Lnk lk, const Vec* x, V
     y[i] = (Vec)v;
 }
 
+// The same in FP64 for even nx, two x-adjacent sites per lane with 16-byte
+// accesses; each site's arithmetic is that of k_apply_M, in the same order.
+template <bool TRANSPOSE, int D>
+__global__ __launch_bounds__(256) void k_apply_M2(Geom g, const double* __restrict__ A,
+                                                  const double* __restrict__ x,
+                                                  double* __restrict__ y) {
+    const int i = 2 * (blockIdx.x * 256 + threadIdx.x);  // first site of the pair
+    if (i >= g.V) return;
+    const int s = fdiv(i, g.fvs), n = i - s * g.vs;
+    const D2 xc = ld2(x + i);
+    double hop_a = 0.0, hop_b = 0.0;
+    int rest = n, stride = 1;
+#pragma unroll
+    for (int j = 0; j < D; ++j) {
+        const int q = j + 1 < D ? fdiv(rest, g.fnx) : 0;
+        const int cj = j + 1 < D ? rest - q * g.nx : rest;
+        if (j == 0) {
+            // cj is even: a = cj, b = cj + 1 < nx
+            const double left_a = x[i + (cj == 0 ? g.nx - 1 : -1)];
+            const double right_b = x[i + (cj + 2 == g.nx ? 2 - g.nx : 2)];
+            hop_a += xc.b + left_a;
+            hop_b += right_b + xc.a;
+        } else {
+            const int cpj = cj + 1 == g.nx ? 0 : cj + 1;
+            const int cmj = cj == 0 ? g.nx - 1 : cj - 1;
+            const D2 pl = ld2(x + i + (cpj - cj) * stride);
+            const D2 mi = ld2(x + i + (cmj - cj) * stride);
+            hop_a += pl.a + mi.a;
+            hop_b += pl.b + mi.b;
+        }
+        stride *= g.nx;
+        rest = q;
+    }
+    double va = xc.a - g.kappa * hop_a;
+    double vb = xc.b - g.kappa * hop_b;
+    if (!TRANSPOSE) {
+        const int sm = s == 0 ? g.nt - 1 : s - 1;
+        const D2 a = ld2(A + i), xm = ld2(x + n + sm * g.vs);
+        va += a.a * xm.a;
+        vb += a.b * xm.b;
+    } else {
+        const int sp = s == g.nt - 1 ? 0 : s + 1;
+        const int ip = n + sp * g.vs;
+        const D2 a = ld2(A + ip), xp = ld2(x + ip);
+        va += a.a * xp.a;
+        vb += a.b * xp.b;
+    }
+    st2(y + i, va, vb);
+}
+
 }  // namespace hub
