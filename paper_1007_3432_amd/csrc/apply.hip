@@ -101,18 +101,54 @@ __global__ __launch_bounds__(256) void k_links(Geom g, const double* __restrict_
     }
 }
 
+// The same for even nx, two x-adjacent sites per lane (one 16-byte load of
+// sigma, one store of both links); each site's arithmetic is k_links'.
+template <class T>
+__global__ __launch_bounds__(256) void k_links2(Geom g, const double* __restrict__ sigma,
+                                                T* __restrict__ out) {
+    const int i = 2 * (blockIdx.x * 256 + threadIdx.x);  // first site of the pair
+    if (i >= g.V) return;
+    const int s = fdiv(i, g.fvs), n = i - s * g.vs;
+    const int sm = s == 0 ? g.nt - 1 : s - 1;
+    const double2 sg = *reinterpret_cast<const double2*>(sigma + n + sm * g.vs);
+    const double sa = sin(sg.x), sb = sin(sg.y);
+    typedef T t2 __attribute__((ext_vector_type(2)));
+    t2 v;
+    if constexpr (sizeof(T) == 2) {
+        v.x = (T)sa;  // single round-to-nearest double -> half
+        v.y = (T)sb;
+    } else {
+        const double la = g.lscale * (1.0 + g.b * sa);
+        const double lb = g.lscale * (1.0 + g.b * sb);
+        v.x = (T)(s == 0 ? la : -la);
+        v.y = (T)(s == 0 ? lb : -lb);
+    }
+    *reinterpret_cast<t2*>(out + i) = v;
+}
+
 hub_status launch_links(const Geom& g, const double* sigma, void* links,
                         hub_dtype link, hipStream_t st) {
-    const int grid = ceil_div(g.V, 256);
+    // Even nx: two sites per lane (every row, hence V, is even).
+    const bool pairs = (g.nx & 1) == 0;
+    const int grid = pairs ? ceil_div(g.V / 2, 256) : ceil_div(g.V, 256);
     switch (link) {
         case HUB_F64:
-            k_links<double><<<grid, 256, 0, st>>>(g, sigma, (double*)links);
+            if (pairs)
+                k_links2<double><<<grid, 256, 0, st>>>(g, sigma, (double*)links);
+            else
+                k_links<double><<<grid, 256, 0, st>>>(g, sigma, (double*)links);
             break;
         case HUB_F32:
-            k_links<float><<<grid, 256, 0, st>>>(g, sigma, (float*)links);
+            if (pairs)
+                k_links2<float><<<grid, 256, 0, st>>>(g, sigma, (float*)links);
+            else
+                k_links<float><<<grid, 256, 0, st>>>(g, sigma, (float*)links);
             break;
         case HUB_F16:
-            k_links<_Float16><<<grid, 256, 0, st>>>(g, sigma, (_Float16*)links);
+            if (pairs)
+                k_links2<_Float16><<<grid, 256, 0, st>>>(g, sigma, (_Float16*)links);
+            else
+                k_links<_Float16><<<grid, 256, 0, st>>>(g, sigma, (_Float16*)links);
             break;
     }
     HUB_HIP(hipGetLastError());
