@@ -35,6 +35,10 @@
  *     t_hop >= 0, dtau > 0, U <= 0, all values finite.
  *   - Precision pairs (vector dtype, link dtype) accepted by the apply calls:
  *     (HUB_F64, HUB_F64), (HUB_F32, HUB_F32), (HUB_F32, HUB_F16).
+ *   - The solvers (hub_cg_solve, hub_pcg_solve, the HMC calls) run on the
+ *     device current on the calling host thread; a host thread keeps to one
+ *     device for them (a solve on another device returns HUB_E_INVALID;
+ *     use another thread).
  *   - No C++ exception crosses this interface.
  */
 #ifndef HUB_H
