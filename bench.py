@@ -352,6 +352,56 @@ def sweep_rate(hub, shape, sets: int, calls: int, vec=None):
             "sweep_vs_stream_add": add_us / us}
 
 
+def row_rates(hub, shape, sets: int, calls: int):
+    """The single-operator rows on one lattice, FP64: links from sigma (8 B in,
+    8 B out per site), M and M^T (x and A in, y out: 24 B/site algorithmic,
+    the neighbours' re-reads served by the caches).  `calls` launches over
+    `sets` rotating buffer sets, captured into one HIP graph; HIP events
+    around a replay."""
+    import torch
+    from paper_1007_3432_amd import inputs
+    d, nx, nt = shape
+    lat = hub.lattice(d, nx, nt)
+    V = lat.volume
+    sigma, _ = inputs.sigma_eta(d, nx, nt, seed=0)
+    sig = [_dev(sigma) for _ in range(sets)]
+    links = [torch.empty(V, dtype=torch.float64, device="cuda:0") for _ in range(sets)]
+    xs = [_dev(inputs.random_vector(V, 300 + k)) for k in range(sets)]
+    ys = [torch.empty(V, dtype=torch.float64, device="cuda:0") for _ in range(sets)]
+    for k in range(sets):
+        hub.hub_links_from_sigma(lat, sig[k], links[k], hub.F64)
+    torch.cuda.synchronize()
+
+    def rate(body, bytes_per_site):
+        body()
+        torch.cuda.synchronize()
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g):
+            body()
+        g.replay()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        g.replay()
+        e1.record()
+        torch.cuda.synchronize()
+        us = e0.elapsed_time(e1) * 1e3 / calls
+        gbs = bytes_per_site * V / us / 1e3
+        return {"avg_launch_us": us, "bytes_per_site": bytes_per_site, "achieved_gbs": gbs,
+                "frac": gbs / HBM_PEAK_GBS}
+
+    out = {"shape": list(shape), "sites": V, "sets": sets, "calls": calls}
+    out["a1_links_f64"] = rate(lambda: [hub.hub_links_from_sigma(lat, sig[c % sets],
+                                                                   links[c % sets], hub.F64)
+                                        for c in range(calls)], 16)
+    for name, tr in (("a2_apply_M_f64", 0), ("a3_apply_Mt_f64", 1)):
+        out[name] = rate(lambda tr=tr: [hub.hub_apply_M(lat, links[c % sets], hub.F64, hub.F64,
+                                                        xs[c % sets], ys[c % sets], tr)
+                                        for c in range(calls)], 24)
+    del sig, links, xs, ys
+    return out
+
+
 def cg_profile_leg(hub, iters: int):
     """A fixed number of CG iterations per solver on c2 and c3 (the solves
     stop at max_iter): a short, representative kernel mix for counter runs."""
@@ -915,6 +965,11 @@ def main():
         detail["sweep_c2_d3_16x160"] = sweep_rate(hub, (3, 16, 160), 24, 500)
         detail["sweep_c3_d3_32x256"] = sweep_rate(hub, (3, 32, 256), 3, 60)
         detail["sweep_d1_8192x1024"] = sweep_rate(hub, (1, 8192, 1024), 3, 60)
+        torch.cuda.empty_cache()
+        # The single-operator rows (links, M, M^T) on c1 and c3, streamed
+        # from HBM (rotating sets larger than the Infinity Cache).
+        detail["rows_c1_d1_2048x512"] = row_rates(hub, (1, 2048, 512), 24, 240)
+        detail["rows_c3_d3_32x256"] = row_rates(hub, (3, 32, 256), 3, 30)
         torch.cuda.empty_cache()
     if "cgprof" in legs:
         _progress(f"cgprof: {a.cgprof_iters} iterations per solver on c2 and c3")
