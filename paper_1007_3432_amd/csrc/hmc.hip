@@ -30,7 +30,7 @@ template <int MODE, int D>
 __global__ __launch_bounds__(256) void k_force(Geom g, double* __restrict__ sigma,
                                                const double* __restrict__ x,
                                                double* __restrict__ out, double c, double eps) {
-    const int i = blockIdx.x * 256 + threadIdx.x;
+    const int i = xcd_remap(blockIdx.x, gridDim.x) * 256 + threadIdx.x;
     if (i >= g.V) return;
     const int s = fdiv(i, g.fvs), n = i - s * g.vs;
     const int sp = s + 1 == g.nt ? 0 : s + 1;
@@ -72,7 +72,7 @@ template <int MODE, int D>
 __global__ __launch_bounds__(256) void k_force2(Geom g, double* __restrict__ sigma,
                                                 const double* __restrict__ x,
                                                 double* __restrict__ out, double c, double eps) {
-    const int i = 2 * (blockIdx.x * 256 + threadIdx.x);  // first site of the pair
+    const int i = 2 * (xcd_remap(blockIdx.x, gridDim.x) * 256 + threadIdx.x);  // first site of the pair
     if (i >= g.V) return;
     const int s = fdiv(i, g.fvs), n = i - s * g.vs;
     const int sp = s + 1 == g.nt ? 0 : s + 1;

@@ -1141,7 +1141,7 @@ template <class Op>
 __global__ __launch_bounds__(256) void k_gen_pass1(Geom g, Op op, typename Op::acc_t* y) {
     if (op.skip()) return;
     if (!op.begin()) return;
-    const int i = blockIdx.x * 256 + threadIdx.x;
+    const int i = xcd_remap(blockIdx.x, gridDim.x) * 256 + threadIdx.x;
     if (i < g.V) y[i] = gen_M_at(g, op, i);
 }
 
@@ -1152,7 +1152,8 @@ __global__ __launch_bounds__(256) void k_gen_pass2(Geom g, Op op,
     using Acc = typename Op::acc_t;
     if (op.skip()) return;
     if (!op.begin()) return;
-    const int i = blockIdx.x * 256 + threadIdx.x;
+    const int tile = xcd_remap(blockIdx.x, gridDim.x);
+    const int i = tile * 256 + threadIdx.x;
     double part[Op::kNP] = {};
     if (i < g.V) {
         const int s = fdiv(i, g.fvs), n = i - s * g.vs;
@@ -1174,14 +1175,14 @@ __global__ __launch_bounds__(256) void k_gen_pass2(Geom g, Op op,
         const Acc v = op_in_center(op, i, c);
         op.out(i, zv, v, c, part);
     }
-    if constexpr (Op::kReduce) deposit<256, Op::kNP>(part, partials, blockIdx.x);
+    if constexpr (Op::kReduce) deposit<256, Op::kNP>(part, partials, tile);
 }
 
 // ---------------------------------------------------------------------------
 // Single M or M^T (hub_apply_M): one lane per site, neighbours through L1/L2.
 template <class Acc, class Vec, class Lnk, bool TRANSPOSE>
 __global__ __launch_bounds__(256) void k_apply_M(Geom g, Lnk lk, const Vec* x, Vec* y) {
-    const int i = blockIdx.x * 256 + threadIdx.x;
+    const int i = xcd_remap(blockIdx.x, gridDim.x) * 256 + threadIdx.x;
     if (i >= g.V) return;
     const int s = fdiv(i, g.fvs), n = i - s * g.vs;
     Acc hop = 0;
@@ -1213,7 +1214,7 @@ template <bool TRANSPOSE, int D>
 __global__ __launch_bounds__(256) void k_apply_M2(Geom g, const double* __restrict__ A,
                                                   const double* __restrict__ x,
                                                   double* __restrict__ y) {
-    const int i = 2 * (blockIdx.x * 256 + threadIdx.x);  // first site of the pair
+    const int i = 2 * (xcd_remap(blockIdx.x, gridDim.x) * 256 + threadIdx.x);  // first site of the pair
     if (i >= g.V) return;
     const int s = fdiv(i, g.fvs), n = i - s * g.vs;
     const D2 xc = ld2(x + i);
